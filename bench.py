@@ -1,0 +1,269 @@
+"""Benchmark of the DAS -> envelope -> log-compression B-mode path on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pwi]
+                    [--no-cpu-baseline] [--latency-frames N]
+
+A step is one frame through the whole hot path - DAS (PWI or STAI), the FFT
+analytic-signal envelope with per-column maxima, and the dB log compression
+with clipping - on int16 RF already resident in HBM.  Default workload: PWI,
+64 plane waves over +-16 deg x 128 channels x 2048 samples, 1024 x 512 grid
+over 5-30 mm, synthetic cyst phantom (seeded).
+
+Prints ONE JSON line (rank 0) with the B-mode frame rate, DAS throughput in
+nominal contributions per second (pixel x transmit x channel), frame latency
+percentiles, a roofline object for the dominant kernel (DAS, bound by the
+vector ALU) and the FP64 CPU oracle timed on a bounded sample of the same
+frame.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz retire 39.3e12 vector
+# lane-instructions per second without packed-FP32 dual issue; the published
+# 157.3 TFLOP/s FP32 vector peak is that rate x 2 (FMA) x 2 (packed).
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# algorithmic lane-ops of one active contribution: transmit + receive delay
+# add, index / fraction split, r[n+1] - r[n], interpolating FMA, accumulate
+OPS_PER_CONTRIB = 5
+
+PAPER_CONTEXT = {
+    "source": "WaveFlow (arXiv 1811.01566) Table I, NVIDIA Titan X, TF 1.6, float64 input",
+    "stai_fps": 55, "pwi_fps": 17,
+    "stai_shape": "(128, 64, 2048) -> (2048, 128)", "pwi_shape": "(11, 192, 2048) -> (512, 128)",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="pwi", choices=["pwi", "stai_full", "stai_small",
+                                                          "pwi_batch8", "paper_stai",
+                                                          "paper_pwi"])
+    ap.add_argument("--latency-frames", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-columns", type=int, default=48,
+                    help="image columns of the frame the CPU oracle computes")
+    return ap.parse_args()
+
+
+def active_contributions(w):
+    """Pixel x transmit x channel triples whose echo sample lies inside the
+    record and whose channel is inside the receive aperture (float64)."""
+    import numpy as np
+
+    import oracle
+
+    g = w.grid()
+    # every 8th row and column is an unbiased sample of the fraction
+    iz = np.arange(0, w.nz, 8)
+    ix = np.arange(0, w.nx, 8)
+    IZ, IX = np.meshgrid(iz, ix, indexing="ij")
+    ttx, trx = oracle.workload_tof(w, IZ, IX)
+    x = g["x0"] + IX * g["dx"]
+    z = g["z0"] + IZ * g["dz"]
+    ex = oracle.element_positions(w.n_elem, w.pitch)[w.rx_elements()]
+    act = 0
+    for t in range(w.n_tx):
+        u = (ttx[t][None] + trx - w.t0) * w.fs
+        n = np.floor(u)
+        ok = (n >= 0) & (n <= w.n_s - 2)
+        if w.f_number > 0:
+            ok &= 2 * w.f_number * np.abs(x[None] - ex[:, None, None]) <= z[None]
+        act += int(ok.sum())
+    frac = act / (w.n_tx * w.n_ch * IZ.size)
+    return frac
+
+
+def scan_of(wf, w):
+    """Binding geometry of a synthetic workload."""
+    g = w.grid()
+    kw = dict(mode=w.mode, n_elem=w.n_elem, pitch=w.pitch, c=w.c, fs=w.fs, n_tx=w.n_tx,
+              n_ch=w.n_ch, grid=wf.Grid(g["nz"], g["nx"], g["z0"], g["dz"], g["x0"], g["dx"]),
+              t0=w.t0, f_number=w.f_number,
+              rx_elem=tuple(w.rx_elem) if w.rx_elem is not None else None)
+    if w.mode == "stai":
+        kw["tx_elem"] = tuple(w.tx_elements())
+    else:
+        kw["angles_rad"] = tuple(w.angles_rad())
+        kw["tref"] = w.tref
+    return wf.Scan(**kw)
+
+
+def cpu_baseline(w, rf, ncols):
+    """The FP64 oracle on `ncols` whole columns of one frame (DAS, envelope,
+    log compression), scaled to frames/s."""
+    import numpy as np
+
+    import oracle
+
+    cols = np.linspace(0, w.nx - 1, ncols).round().astype(int)
+    iz = np.repeat(np.arange(w.nz), ncols).reshape(w.nz, ncols)
+    ix = np.tile(cols, (w.nz, 1))
+    rf64 = rf[0].astype(np.float64)
+    t0 = time.perf_counter()
+    y = oracle.das_workload(rf64, w, iz, ix)
+    b = oracle.log_compress(oracle.envelope(y), w.dr_db)
+    dt = time.perf_counter() - t0
+    del b
+    frac = ncols / w.nx
+    s_per_frame = dt / frac
+    return {
+        "value": 1.0 / s_per_frame, "unit": "frames/s", "cores": 1, "kind": "oracle",
+        "sample": f"{ncols} of {w.nx} columns x {w.nz} rows of one frame, all "
+                  f"{w.n_tx}x{w.n_ch} transmit/channel pairs, float64 NumPy, "
+                  f"{dt:.1f} s measured, scaled by {w.nx}/{ncols}",
+        "s_per_frame": s_per_frame,
+        "host_cpus": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the DAS path needs no collective and this build "
+              "measures a single MI355X (--gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_01566_amd as wf
+    import phantom
+
+    w = phantom.get_workload(args.workload)
+    # synthesise before the GPU is initialised (the generator forks workers)
+    print(f"[bench] synthesising {w.name} RF ...", file=sys.stderr, flush=True)
+    t_syn = time.perf_counter()
+    rf_np = phantom.synth_rf(w)
+    print(f"[bench] RF {rf_np.shape} {rf_np.dtype} in {time.perf_counter() - t_syn:.1f} s",
+          file=sys.stderr, flush=True)
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    wf.load()
+    dev = torch.device("cuda:0")
+
+    scan = scan_of(wf, w)
+    rf = torch.from_numpy(rf_np).to(dev)
+    F = w.n_frames
+    y = torch.empty((F, w.nz, w.nx), dtype=torch.float32, device=dev)
+    out = torch.empty_like(y)
+    col_max = torch.empty((F, w.nx), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        wf.das(scan, rf, out=y)
+        wf.bmode(y, w.dr_db, out=out, col_max=col_max)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps, per-kernel HIP events on the same stream --
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        wf.das(scan, rf, out=y)
+        ev[i][1].record(stream)
+        wf.bmode(y, w.dr_db, out=out, col_max=col_max)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    das_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    post_ms = [b.elapsed_time(c) for _, b, c in ev]
+    ms_per_step = wall * 1e3 / args.steps
+
+    # ---- per-kernel split of the post-processing (Table I analogue) -------
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    env_ms, logc_ms = [], []
+    for _ in range(10):
+        e0.record(stream)
+        wf.envelope(y, env=out, col_max=col_max)
+        e1.record(stream)
+        wf.log_compress(out, col_max, w.dr_db, out=out)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        env_ms.append(e0.elapsed_time(e1))
+        logc_ms.append(e1.elapsed_time(e2))
+
+    # ---- closed-loop frame latency: enqueue -> completion, one in flight --
+    lat = []
+    for _ in range(args.latency_frames):
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat = np.asarray(lat)
+
+    fps = F * args.steps / wall
+    das_avg_s = float(np.mean(das_ms)) * 1e-3
+    nominal = w.nominal_contributions
+    act_frac = active_contributions(w)
+    achieved = OPS_PER_CONTRIB * act_frac * nominal / das_avg_s
+    res = {
+        "metric": "B-mode frames/s + DAS Gsamples/s (PWI 128ch×64tx); p99 frame latency",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "mode": w.mode, "frames_per_step": F, "n_tx": w.n_tx, "n_ch": w.n_ch,
+            "n_s": w.n_s, "grid": [w.nz, w.nx], "rf_dtype": "int16",
+            "depth_mm": [w.z_min * 1e3, w.z_max * 1e3], "f_number": w.f_number,
+            "dr_db": w.dr_db,
+        },
+        "das_gsamples_per_s": round(nominal / das_avg_s / 1e9, 2),
+        "das_gsamples_per_s_active": round(act_frac * nominal / das_avg_s / 1e9, 2),
+        "active_fraction": round(act_frac, 4),
+        "step_ms": {"das": round(float(np.mean(das_ms)), 4),
+                    "envelope": round(float(np.mean(env_ms)), 4),
+                    "log_compress": round(float(np.mean(logc_ms)), 4),
+                    "envelope_plus_log": round(float(np.mean(post_ms)), 4)},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "frames": int(lat.size)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "das_kernel",
+            "achieved": round(achieved / 1e12, 3),
+            "peak": round(PEAK_LANE_OPS / 1e12, 2),
+            "unit": "Tops/s (vector lane-ops)",
+            "frac": round(achieved / PEAK_LANE_OPS, 4),
+            "traffic": None,
+            "ops_per_launch": OPS_PER_CONTRIB * act_frac * nominal,
+            "avg_launch_ms": round(das_avg_s * 1e3, 4),
+        },
+        "paper_context": PAPER_CONTEXT,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, rf_np, args.cpu_columns)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * wf.h - C ABI of libwf: Delay-and-Sum beamforming (STAI and PWI), analytic-
+ * signal envelope, and log compression with dynamic-range clipping into a
+ * B-mode frame, on one AMD Instinct MI355X (gfx950).
+ *
+ * The pipeline is the B-mode reconstruction of the WaveFlow paper (arXiv
+ * 1811.01566): Beamforming -> Analytic Signal -> Absolute Value -> Dynamic
+ * Adjustment (Fig. 2), with DAS for synthetic transmit aperture (STAI) and
+ * plane-wave (PWI) imaging as the mid-processing op (Sec. II-B), the
+ * analytic signal formed with the FFT-based Hilbert transform (Sec. II-B),
+ * and the frame clipped to a dB range (Sec. III).  The inputs follow the
+ * paper's Ultrasound Environment (Sec. II-A): an RF tensor (acquisitions,
+ * channels, samples) plus metadata - speed of sound, aperture, sampling
+ * frequency.
+ *
+ * Conventions shared by every call (the paper gives no equations; these are
+ * the readings the library implements):
+ *  - Linear array on z = 0; element e at x_e = (e - (N-1)/2) * pitch unless
+ *    an explicit host array of positions is given.  z is depth (> 0 into
+ *    the medium).  Pixel (iz, ix) is at (x0 + ix*dx, z0 + iz*dz), metres.
+ *  - Times of flight: receive |p - e_j| / c; STAI transmit t (one element
+ *    e_t fires) |p - e_t| / c; PWI transmit k (angle theta_k, > 0 steers
+ *    towards +x) (z cos theta_k + x sin theta_k + o_k) / c, with
+ *    o_k = -min_e(x_e sin theta_k) (time zero when the first element fires)
+ *    or o_k = 0 (time zero when the wavefront crosses x = 0).
+ *  - Sample s of the record is taken at t0 + s/fs.  u = (tau_tx + tau_rx -
+ *    t0) * fs; n = floor(u); the contribution is the linear interpolation
+ *    (1-a) r[n] + a r[n+1], a = u - n, and 0 unless 0 <= n <= S-2.
+ *  - Receive apodisation (f_number > 0): channel j counts for pixel p iff
+ *    2 * f_number * |x - x_j| <= z.  No transmit apodisation, no
+ *    normalisation; PWI compounding is the plain sum over angles.
+ *  - Every array is dense, row-major, last index fastest.
+ *
+ * Memory and streams.  Pointers documented as DEVICE are HIP device
+ * pointers on the current device; HOST pointers are read during the call
+ * only.  Every compute call is asynchronous on `stream` (a hipStream_t
+ * passed as void*, NULL = the null stream); the library never synchronises
+ * the stream.  The caller owns every buffer.  The only memory the library
+ * allocates is a small per-geometry constant table (transmit and element
+ * constants, a few KB) that it uploads with a blocking copy the first time
+ * a geometry is seen on a device and keeps for the life of the process
+ * (wf_geometry_cache_clear() frees it); do not make that first call while
+ * the stream is being captured into a graph.
+ *
+ * Errors.  Every call validates all arguments before touching the device
+ * and returns a negative wf_status with a message from wf_last_error() on
+ * failure; nothing is launched then.  Faults inside kernels surface at the
+ * caller's next synchronisation.  Calls are re-entrant; the error string is
+ * per thread.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WF_ABI_VERSION 1
+
+typedef enum {
+    WF_OK = 0,
+    WF_ERR_INVALID_ARG = -1, /* a null pointer, a size or value out of range */
+    WF_ERR_UNSUPPORTED = -2, /* valid, but outside what the kernels handle  */
+    WF_ERR_DEVICE = -3       /* a HIP runtime call failed                   */
+} wf_status;
+
+typedef enum {
+    WF_RF_I16 = 0, /* int16 ADC counts                                    */
+    WF_RF_F16 = 1, /* IEEE half                                           */
+    WF_RF_F32 = 2  /* float                                               */
+} wf_rf_dtype;
+
+typedef enum {
+    WF_PWI_TREF_FIRST = 0, /* time zero: the first element fires          */
+    WF_PWI_TREF_CENTRE = 1 /* time zero: the wavefront crosses x = 0      */
+} wf_pwi_tref;
+
+#define WF_BMODE_OFFSET 1 /* add dr_db so the output spans [0, dr_db] */
+
+typedef struct {
+    int32_t n_elem;       /* number of array elements, 1..4096              */
+    double pitch;         /* element spacing (m), used when elem_x is NULL  */
+    const double* elem_x; /* HOST [n_elem] lateral positions (m), or NULL   */
+} wf_probe;
+
+typedef struct {
+    int32_t nz, nx;       /* pixels along depth and laterally              */
+    double z0, dz;        /* depth of row 0 and row step (m)               */
+    double x0, dx;        /* lateral position of column 0 and step (m)     */
+} wf_grid;
+
+typedef struct {
+    int32_t n_frames;     /* F >= 1 frames sharing the geometry            */
+    int32_t n_tx;         /* T, 1..1024 transmits per frame                */
+    int32_t n_ch;         /* C, 1..1024 receive channels                   */
+    int32_t n_s;          /* S, 16..32768 samples per record, S % 8 == 0   */
+    int32_t dtype;        /* wf_rf_dtype of the RF samples                 */
+    double c;             /* speed of sound (m/s), > 0                     */
+    double fs;            /* sampling frequency (Hz), > 0                  */
+    double t0;            /* time of sample 0 (s)                          */
+    double f_number;      /* receive f-number; 0 disables apodisation      */
+    const int32_t* rx_elem; /* HOST [n_ch] element of each channel, NULL = j */
+} wf_acq;
+
+/*
+ * DAS for synthetic transmit aperture imaging (Sec. II-B; evaluation shape
+ * (acquisitions, channels, samples), Sec. III).  Transmit t fires the single
+ * element tx_elem[t] (HOST [n_tx], NULL = t); the sum runs over transmits
+ * and receive channels.
+ *   rf   DEVICE [F][T][C][S] of acq->dtype, 16-byte aligned.
+ *   out  DEVICE float [F][nz][nx] beamformed RF (real, not IQ); must not
+ *        overlap rf.
+ * Returns WF_ERR_UNSUPPORTED when the pixel spacing is so coarse that no
+ * tile shape keeps a tile's delay spread inside the kernel's window.
+ */
+wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const wf_grid* grid, float* out,
+                      void* stream);
+
+/*
+ * DAS for plane-wave imaging with coherent compounding over angles
+ * (Sec. II-B).  angles_rad: HOST [n_tx] steering angles, |theta| < 80 deg.
+ * tref: wf_pwi_tref.  rf and out as for wf_das_stai.
+ */
+wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
+                     const double* angles_rad, int32_t tref, const wf_grid* grid,
+                     float* out, void* stream);
+
+/*
+ * One-way times of flight in samples as computed on the device (float-float
+ * FP32 arithmetic), for testing the delay geometry of the DAS calls.
+ *   tx_hi, tx_lo  DEVICE float [T][nz][nx]: (tau_tx - t0) * fs = hi + lo
+ *   rx_hi, rx_lo  DEVICE float [C][nz][nx]: tau_rx * fs = hi + lo
+ * For PWI pass angles_rad/tref, for STAI tx_elem; mode 0 = STAI, 1 = PWI.
+ * acq->n_frames, n_s and dtype are ignored.
+ */
+wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                    const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                    const wf_grid* grid, float* tx_hi, float* tx_lo, float* rx_hi,
+                    float* rx_lo, void* stream);
+
+/*
+ * Envelope = |analytic signal| along depth of every column (Fig. 2:
+ * Analytic Signal -> Absolute Value; Hilbert transform by FFT, Sec. II-B):
+ * an nz-point FFT, the one-sided multiplier (1, 2, ..., 2, 1, 0, ..., 0),
+ * an inverse FFT, the modulus.  nz must be a power of two, 2..4096.
+ *   bf       DEVICE float [F][nz][nx] beamformed RF.
+ *   env      DEVICE float [F][nz][nx]; may be the same buffer as bf.
+ *   col_max  DEVICE float [F][nx]: the maximum envelope of each column.
+ */
+wf_status wf_envelope(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
+                      float* env, float* col_max, void* stream);
+
+/*
+ * Log compression and clip (Fig. 2 "Dynamic Adjustment"; [0, DR] dB range,
+ * Sec. III): B = 20 log10(env / m_f) clipped to [-dr_db, 0], m_f the frame
+ * maximum (the maximum of col_max[f][:]); env = 0 or m_f = 0 gives -dr_db;
+ * flags & WF_BMODE_OFFSET adds dr_db.
+ *   env      DEVICE float [F][nz][nx] (>= 0).
+ *   col_max  DEVICE float [F][nx] as written by wf_envelope.
+ *   out_db   DEVICE float [F][nz][nx]; may be the same buffer as env.
+ */
+wf_status wf_log_compress(const float* env, const float* col_max, int32_t n_frames,
+                          int32_t nz, int32_t nx, float dr_db, int32_t flags,
+                          float* out_db, void* stream);
+
+/*
+ * Beamformed RF -> B-mode frame: wf_envelope into out_db, then
+ * wf_log_compress in place.  col_max: DEVICE float [F][nx] scratch.
+ * out_db must not overlap bf.
+ */
+wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
+                   float dr_db, int32_t flags, float* out_db, float* col_max,
+                   void* stream);
+
+/* Message of the last failed call on this thread ("" after success). */
+const char* wf_last_error(void);
+
+/* WF_ABI_VERSION of the loaded library. */
+int32_t wf_abi_version(void);
+
+/* Free the cached per-geometry constant tables on every device.  Must not
+ * run while work that uses them is in flight. */
+wf_status wf_geometry_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WF_H */

@@ -1,0 +1,265 @@
+"""MI355X-native DAS -> envelope -> B-mode path (WaveFlow, arXiv 1811.01566).
+
+Thin Python binding over ``libwf.so`` (C ABI in ``include/wf.h``): it
+marshals arguments and passes torch device pointers and the current HIP
+stream; every step of the path runs in the library's HIP kernels.  There is
+no CPU fallback: calls fail when the library is missing or the tensors are
+not on a GPU.
+
+Pipeline (paper Fig. 2): :func:`das_stai` / :func:`das_pwi` (Beamforming,
+Sec. II-B) -> :func:`envelope` (Analytic Signal + Absolute Value) ->
+:func:`log_compress` (Dynamic Adjustment, dB clip of Sec. III); :func:`bmode`
+runs the last two.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import WfError, load
+
+__all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
+           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear"]
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Pixel grid: pixel (iz, ix) at (x0 + ix*dx, z0 + iz*dz), metres."""
+    nz: int
+    nx: int
+    z0: float
+    dz: float
+    x0: float
+    dx: float
+
+
+@dataclass(frozen=True)
+class Scan:
+    """Probe, transmit sequence and grid of one acquisition geometry.
+
+    mode "stai": transmit t fires element tx_elem[t] (default t).
+    mode "pwi": transmit t is a plane wave at angles_rad[t]; tref "first"
+    (time zero when the first element fires) or "centre".
+    """
+    mode: str
+    n_elem: int
+    pitch: float
+    c: float
+    fs: float
+    n_tx: int
+    n_ch: int
+    grid: Grid
+    t0: float = 0.0
+    f_number: float = 0.0
+    tx_elem: Optional[Sequence[int]] = None
+    angles_rad: Optional[Sequence[float]] = None
+    tref: str = "first"
+    rx_elem: Optional[Sequence[int]] = None
+    elem_x: Optional[Sequence[float]] = None
+
+    def das(self, rf, out=None, stream=None):
+        return das(self, rf, out=out, stream=stream)
+
+
+def abi_version() -> int:
+    return int(load().wf_abi_version())
+
+
+def geometry_cache_clear() -> None:
+    _lib.check(load().wf_geometry_cache_clear(), "wf_geometry_cache_clear")
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr(t, stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _Keep:
+    """Holds ctypes arrays alive for the duration of a call."""
+
+    def __init__(self):
+        self.items = []
+
+    def arr(self, ctype, values):
+        if values is None:
+            return None
+        a = (ctype * len(values))(*values)
+        self.items.append(a)
+        return ctypes.cast(a, ctypes.POINTER(ctype))
+
+
+def _structs(scan: Scan, keep: _Keep, n_frames=1, n_s=0, dtype=0):
+    probe = _lib.WfProbe(int(scan.n_elem), float(scan.pitch),
+                         keep.arr(ctypes.c_double, scan.elem_x))
+    acq = _lib.WfAcq(int(n_frames), int(scan.n_tx), int(scan.n_ch), int(n_s), int(dtype),
+                     float(scan.c), float(scan.fs), float(scan.t0), float(scan.f_number),
+                     keep.arr(ctypes.c_int32, scan.rx_elem))
+    g = scan.grid
+    grid = _lib.WfGrid(int(g.nz), int(g.nx), float(g.z0), float(g.dz), float(g.x0), float(g.dx))
+    return probe, acq, grid
+
+
+def _tref(scan):
+    if scan.tref == "first":
+        return _lib.WF_PWI_TREF_FIRST
+    if scan.tref == "centre":
+        return _lib.WF_PWI_TREF_CENTRE
+    raise ValueError(f"tref must be 'first' or 'centre', got {scan.tref!r}")
+
+
+def _rf_dtype(t):
+    torch = _torch()
+    m = {torch.int16: _lib.WF_RF_I16, torch.float16: _lib.WF_RF_F16,
+         torch.float32: _lib.WF_RF_F32}
+    if t.dtype not in m:
+        raise TypeError(f"rf dtype {t.dtype} is not int16, float16 or float32")
+    return m[t.dtype]
+
+
+# ---------------------------------------------------------------------------
+# public calls
+# ---------------------------------------------------------------------------
+
+def das(scan: Scan, rf, out=None, stream=None):
+    """Delay-and-Sum of rf [F][T][C][S] (or [T][C][S]) -> float32 [F][nz][nx]
+    (or [nz][nx])."""
+    torch = _torch()
+    lib = load()
+    squeeze = rf.dim() == 3
+    rf4 = rf.unsqueeze(0) if squeeze else rf
+    if rf4.dim() != 4:
+        raise ValueError("rf must be [F][T][C][S] or [T][C][S]")
+    nf, nt, nc, ns = rf4.shape
+    if nt != scan.n_tx or nc != scan.n_ch:
+        raise ValueError(f"rf shape {tuple(rf.shape)} does not match n_tx={scan.n_tx}, "
+                         f"n_ch={scan.n_ch}")
+    g = scan.grid
+    if out is None:
+        out = torch.empty((nf, g.nz, g.nx), dtype=torch.float32, device=rf.device)
+    elif out.dtype != torch.float32 or out.numel() != nf * g.nz * g.nx:
+        raise ValueError("out must be float32 with F*nz*nx elements")
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
+    rfp, outp, st = _dev(rf4, "rf"), _dev(out, "out"), _stream_ptr(rf4, stream)
+    if scan.mode == "stai":
+        tx = keep.arr(ctypes.c_int32, scan.tx_elem)
+        _lib.check(lib.wf_das_stai(rfp, probe, acq, tx, grid, outp, st), "wf_das_stai")
+    elif scan.mode == "pwi":
+        ang = keep.arr(ctypes.c_double, scan.angles_rad)
+        _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, outp, st),
+                   "wf_das_pwi")
+    else:
+        raise ValueError(f"mode must be 'stai' or 'pwi', got {scan.mode!r}")
+    out = out.view(nf, g.nz, g.nx)
+    return out[0] if squeeze else out
+
+
+def das_stai(rf, scan: Scan, out=None, stream=None):
+    if scan.mode != "stai":
+        raise ValueError("scan.mode must be 'stai'")
+    return das(scan, rf, out, stream)
+
+
+def das_pwi(rf, scan: Scan, out=None, stream=None):
+    if scan.mode != "pwi":
+        raise ValueError("scan.mode must be 'pwi'")
+    return das(scan, rf, out, stream)
+
+
+def delays(scan: Scan, device="cuda", stream=None):
+    """Device-computed one-way delays in samples as float64 tensors:
+    (tx [T][nz][nx] = (tau_tx - t0) fs, rx [C][nz][nx] = tau_rx fs)."""
+    torch = _torch()
+    lib = load()
+    g = scan.grid
+    mk = lambda n: torch.empty((n, g.nz, g.nx), dtype=torch.float32, device=device)
+    txh, txl, rxh, rxl = mk(scan.n_tx), mk(scan.n_tx), mk(scan.n_ch), mk(scan.n_ch)
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep)
+    mode = 0 if scan.mode == "stai" else 1
+    tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
+    ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
+    tref = _tref(scan) if mode == 1 else 0
+    _lib.check(lib.wf_delays(mode, probe, acq, tx, ang, tref, grid, _dev(txh, "tx_hi"),
+                             _dev(txl, "tx_lo"), _dev(rxh, "rx_hi"), _dev(rxl, "rx_lo"),
+                             _stream_ptr(txh, stream)), "wf_delays")
+    return (txh.double() + txl.double(), rxh.double() + rxl.double())
+
+
+def envelope(bf, env=None, col_max=None, stream=None):
+    """|analytic signal| along depth of bf [F][nz][nx] (or [nz][nx]);
+    returns (env, col_max [F][nx])."""
+    torch = _torch()
+    lib = load()
+    squeeze = bf.dim() == 2
+    b3 = bf.unsqueeze(0) if squeeze else bf
+    nf, nz, nx = b3.shape
+    if env is None:
+        env = torch.empty_like(b3)
+    if col_max is None:
+        col_max = torch.empty((nf, nx), dtype=torch.float32, device=bf.device)
+    _lib.check(lib.wf_envelope(_dev(b3, "bf"), nf, nz, nx, _dev(env, "env"),
+                               _dev(col_max, "col_max"), _stream_ptr(b3, stream)), "wf_envelope")
+    env = env.view(nf, nz, nx)
+    return (env[0] if squeeze else env), col_max
+
+
+def log_compress(env, col_max, dr_db: float, offset: bool = False, out=None, stream=None):
+    torch = _torch()
+    lib = load()
+    squeeze = env.dim() == 2
+    e3 = env.unsqueeze(0) if squeeze else env
+    nf, nz, nx = e3.shape
+    if out is None:
+        out = torch.empty_like(e3)
+    flags = _lib.WF_BMODE_OFFSET if offset else 0
+    _lib.check(lib.wf_log_compress(_dev(e3, "env"), _dev(col_max, "col_max"), nf, nz, nx,
+                                   float(dr_db), flags, _dev(out, "out"),
+                                   _stream_ptr(e3, stream)), "wf_log_compress")
+    out = out.view(nf, nz, nx)
+    return out[0] if squeeze else out
+
+
+def bmode(bf, dr_db: float, offset: bool = False, out=None, col_max=None, stream=None):
+    """Beamformed RF -> B-mode dB frame (envelope, frame max, 20 log10, clip)."""
+    torch = _torch()
+    lib = load()
+    squeeze = bf.dim() == 2
+    b3 = bf.unsqueeze(0) if squeeze else bf
+    nf, nz, nx = b3.shape
+    if out is None:
+        out = torch.empty_like(b3)
+    if col_max is None:
+        col_max = torch.empty((nf, nx), dtype=torch.float32, device=bf.device)
+    flags = _lib.WF_BMODE_OFFSET if offset else 0
+    _lib.check(lib.wf_bmode(_dev(b3, "bf"), nf, nz, nx, float(dr_db), flags, _dev(out, "out"),
+                            _dev(col_max, "col_max"), _stream_ptr(b3, stream)), "wf_bmode")
+    out = out.view(nf, nz, nx)
+    return out[0] if squeeze else out

@@ -1,0 +1,490 @@
+// C entry points of libwf: argument validation, per-geometry constant
+// tables, tile selection and stream-ordered kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wf.h"
+#include "wf_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+wf_status fail(wf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+wf_status ok() {
+    g_err.clear();
+    return WF_OK;
+}
+
+wf_status hip_fail(hipError_t e, const char* what) {
+    return fail(WF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+float2 split(double v) {
+    const float h = (float)v;
+    return make_float2(h, (float)(v - (double)h));
+}
+
+constexpr int kMaxTx = 1024;
+constexpr int kMaxCh = 1024;
+constexpr int kMaxElem = 4096;
+constexpr double kMaxAngle = 80.0 * M_PI / 180.0;
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+wf_status check_geometry(int mode, const wf_probe* probe, const wf_acq* acq,
+                         const int32_t* tx_elem, const double* angles, int32_t tref,
+                         const wf_grid* grid, bool need_rf) {
+    if (!probe) return fail(WF_ERR_INVALID_ARG, "probe is NULL");
+    if (!acq) return fail(WF_ERR_INVALID_ARG, "acq is NULL");
+    if (!grid) return fail(WF_ERR_INVALID_ARG, "grid is NULL");
+    if (probe->n_elem < 1 || probe->n_elem > kMaxElem)
+        return fail(WF_ERR_INVALID_ARG, "probe->n_elem=%d outside [1, %d]", probe->n_elem,
+                    kMaxElem);
+    if (probe->elem_x) {
+        for (int e = 0; e < probe->n_elem; ++e)
+            if (!finite(probe->elem_x[e]))
+                return fail(WF_ERR_INVALID_ARG, "probe->elem_x[%d] is not finite", e);
+    } else if (!finite(probe->pitch) || probe->pitch <= 0.0) {
+        return fail(WF_ERR_INVALID_ARG, "probe->pitch must be > 0 when elem_x is NULL");
+    }
+    if (acq->n_tx < 1 || acq->n_tx > kMaxTx)
+        return fail(WF_ERR_INVALID_ARG, "acq->n_tx=%d outside [1, %d]", acq->n_tx, kMaxTx);
+    if (acq->n_ch < 1 || acq->n_ch > kMaxCh)
+        return fail(WF_ERR_INVALID_ARG, "acq->n_ch=%d outside [1, %d]", acq->n_ch, kMaxCh);
+    if (need_rf) {
+        if (acq->n_frames < 1) return fail(WF_ERR_INVALID_ARG, "acq->n_frames must be >= 1");
+        if (acq->n_frames > 65535)
+            return fail(WF_ERR_INVALID_ARG, "acq->n_frames=%d above 65535", acq->n_frames);
+        if (acq->n_s < 16 || acq->n_s > 32768)
+            return fail(WF_ERR_INVALID_ARG, "acq->n_s=%d outside [16, 32768]", acq->n_s);
+        if (acq->n_s % 8 != 0)
+            return fail(WF_ERR_UNSUPPORTED, "acq->n_s=%d is not a multiple of 8", acq->n_s);
+        if (acq->dtype < WF_RF_I16 || acq->dtype > WF_RF_F32)
+            return fail(WF_ERR_INVALID_ARG, "acq->dtype=%d is not a wf_rf_dtype", acq->dtype);
+    }
+    if (!finite(acq->c) || acq->c <= 0.0) return fail(WF_ERR_INVALID_ARG, "acq->c must be > 0");
+    if (!finite(acq->fs) || acq->fs <= 0.0)
+        return fail(WF_ERR_INVALID_ARG, "acq->fs must be > 0");
+    if (!finite(acq->t0)) return fail(WF_ERR_INVALID_ARG, "acq->t0 is not finite");
+    if (!finite(acq->f_number) || acq->f_number < 0.0)
+        return fail(WF_ERR_INVALID_ARG, "acq->f_number must be >= 0");
+    if (acq->rx_elem)
+        for (int j = 0; j < acq->n_ch; ++j)
+            if (acq->rx_elem[j] < 0 || acq->rx_elem[j] >= probe->n_elem)
+                return fail(WF_ERR_INVALID_ARG, "acq->rx_elem[%d]=%d outside [0, %d)", j,
+                            acq->rx_elem[j], probe->n_elem);
+    if (!acq->rx_elem && acq->n_ch > probe->n_elem)
+        return fail(WF_ERR_INVALID_ARG, "n_ch=%d > n_elem=%d with the identity channel map",
+                    acq->n_ch, probe->n_elem);
+    if (grid->nz < 1 || grid->nx < 1 || grid->nz > 65536 || grid->nx > 65536)
+        return fail(WF_ERR_INVALID_ARG, "grid %d x %d outside [1, 65536]^2", grid->nz, grid->nx);
+    if ((long long)grid->nz * grid->nx > (1LL << 28))
+        return fail(WF_ERR_INVALID_ARG, "grid has more than 2^28 pixels");
+    if (!finite(grid->z0) || !finite(grid->dz) || !finite(grid->x0) || !finite(grid->dx))
+        return fail(WF_ERR_INVALID_ARG, "grid origin/step not finite");
+    if (mode == 0) {
+        if (tx_elem)
+            for (int t = 0; t < acq->n_tx; ++t)
+                if (tx_elem[t] < 0 || tx_elem[t] >= probe->n_elem)
+                    return fail(WF_ERR_INVALID_ARG, "tx_elem[%d]=%d outside [0, %d)", t,
+                                tx_elem[t], probe->n_elem);
+        if (!tx_elem && acq->n_tx > probe->n_elem)
+            return fail(WF_ERR_INVALID_ARG, "n_tx=%d > n_elem=%d with tx_elem NULL", acq->n_tx,
+                        probe->n_elem);
+    } else {
+        if (!angles) return fail(WF_ERR_INVALID_ARG, "angles_rad is NULL");
+        for (int t = 0; t < acq->n_tx; ++t)
+            if (!finite(angles[t]) || std::fabs(angles[t]) >= kMaxAngle)
+                return fail(WF_ERR_INVALID_ARG, "angles_rad[%d]=%g outside (-80, 80) deg", t,
+                            angles[t]);
+        if (tref != WF_PWI_TREF_FIRST && tref != WF_PWI_TREF_CENTRE)
+            return fail(WF_ERR_INVALID_ARG, "tref=%d is not a wf_pwi_tref", tref);
+    }
+    // delays must stay in a sane sample range for the fixed-point windows
+    const double k = acq->fs / acq->c;
+    const double zmax = std::max(std::fabs(grid->z0), std::fabs(grid->z0 + (grid->nz - 1) * grid->dz));
+    const double xspan = std::fabs(grid->x0) + std::fabs((grid->nx - 1) * grid->dx);
+    if ((zmax + xspan) * k > 1.0e6 || std::fabs(acq->t0 * acq->fs) > 1.0e6)
+        return fail(WF_ERR_UNSUPPORTED, "grid or t0 reaches beyond 1e6 samples");
+    return WF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-geometry constant tables (device), cached
+// ---------------------------------------------------------------------------
+
+struct Geometry {
+    std::vector<wf::TxConst> tx;
+    std::vector<wf::ChConst> ch;
+    float2 Z0, dZ, dX, O;
+    float x0f, dxf, fnum2;
+    double dzs, dxs;  // |dz|, |dx| in samples
+};
+
+void build_geometry(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                    const double* angles, int32_t tref, const wf_grid* grid, Geometry* g) {
+    const double k = acq->fs / acq->c;  // samples per metre
+    std::vector<double> ex(probe->n_elem);
+    for (int e = 0; e < probe->n_elem; ++e)
+        ex[e] = probe->elem_x ? probe->elem_x[e]
+                              : (e - (probe->n_elem - 1) / 2.0) * probe->pitch;
+    g->Z0 = split(grid->z0 * k);
+    g->dZ = split(grid->dz * k);
+    g->dX = split(grid->dx * k);
+    g->O = split(-acq->t0 * acq->fs);
+    g->x0f = (float)(grid->x0 * k);
+    g->dxf = (float)(grid->dx * k);
+    g->fnum2 = (float)(2.0 * acq->f_number);
+    g->dzs = std::fabs(grid->dz * k);
+    g->dxs = std::fabs(grid->dx * k);
+    g->ch.resize(acq->n_ch);
+    for (int j = 0; j < acq->n_ch; ++j) {
+        const double xe = ex[acq->rx_elem ? acq->rx_elem[j] : j];
+        const float2 d = split((grid->x0 - xe) * k);
+        g->ch[j] = make_float4(d.x, d.y, (float)(xe * k), 0.0f);
+    }
+    g->tx.resize(acq->n_tx);
+    for (int t = 0; t < acq->n_tx; ++t) {
+        wf::TxConst tc{};
+        if (mode == 0) {
+            const double xe = ex[tx_elem ? tx_elem[t] : t];
+            const float2 d = split((grid->x0 - xe) * k);
+            tc.v0 = make_float4(d.x, d.y, (float)(xe * k), 0.0f);
+            tc.v1 = make_float4(0, 0, 0, 0);
+        } else {
+            const double th = angles[t];
+            const double st = std::sin(th), ct = std::cos(th);
+            double o = 0.0;
+            if (tref == WF_PWI_TREF_FIRST) {
+                double mn = ex[0] * st;
+                for (double x : ex) mn = std::min(mn, x * st);
+                o = -mn;
+            }
+            const double c0 = (grid->z0 * ct + grid->x0 * st + o) * k - acq->t0 * acq->fs;
+            const double az = grid->dz * ct * k, ax = grid->dx * st * k;
+            const double azh = std::nearbyint(az * 32768.0) / 32768.0;
+            const double axh = std::nearbyint(ax * 32768.0) / 32768.0;
+            const float2 c0s = split(c0);
+            tc.v0 = make_float4(c0s.x, c0s.y, (float)azh, (float)(az - azh));
+            tc.v1 = make_float4((float)axh, (float)(ax - axh), 0.0f, 0.0f);
+        }
+        g->tx[t] = tc;
+    }
+}
+
+struct CacheEntry {
+    void* dev = nullptr;
+    const wf::TxConst* tx = nullptr;
+    const wf::ChConst* ch = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::string, CacheEntry> g_cache;
+
+void key_add(std::string& k, const void* p, size_t n) { k.append((const char*)p, n); }
+
+wf_status device_tables(int mode, const wf_probe* probe, const wf_acq* acq,
+                        const int32_t* tx_elem, const double* angles, int32_t tref,
+                        const wf_grid* grid, Geometry* g, CacheEntry* out) {
+    build_geometry(mode, probe, acq, tx_elem, angles, tref, grid, g);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::string key;
+    key_add(key, &dev, sizeof dev);
+    key_add(key, &mode, sizeof mode);
+    key_add(key, g->tx.data(), g->tx.size() * sizeof(wf::TxConst));
+    key_add(key, g->ch.data(), g->ch.size() * sizeof(wf::ChConst));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        *out = it->second;
+        return WF_OK;
+    }
+    const size_t txb = g->tx.size() * sizeof(wf::TxConst);
+    const size_t chb = g->ch.size() * sizeof(wf::ChConst);
+    void* mem = nullptr;
+    e = hipMalloc(&mem, txb + chb);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(geometry table)");
+    e = hipMemcpy(mem, g->tx.data(), txb, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)mem + txb, g->ch.data(), chb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "hipMemcpy(geometry table)");
+    }
+    CacheEntry ce;
+    ce.dev = mem;
+    ce.tx = (const wf::TxConst*)mem;
+    ce.ch = (const wf::ChConst*)((char*)mem + txb);
+    g_cache.emplace(key, ce);
+    *out = ce;
+    return WF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// DAS tile selection
+// ---------------------------------------------------------------------------
+
+struct TilePlan {
+    int px = 0, tz_log2 = 0, span = 0, nst = 0, slot = 0;
+    size_t lds = 0;
+    int ntz = 0, ntx = 0;
+};
+
+size_t das_lds_bytes(int slot, int T) {
+    return (size_t)wf::kChunk * slot * 8 + (size_t)((T * 4 + 15) & ~15) + (size_t)T * 8 +
+           (size_t)wf::kChunk * 4;
+}
+
+bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
+    double best_score = -1.0;
+    for (int px : {4, 1}) {
+        for (int tzl = 6; tzl >= 3; --tzl) {
+            const int tz = 1 << tzl;
+            const int txw = (wf::kThreads * px) >> tzl;
+            const int ez = std::min(tz, grid->nz), ex = std::min(txw, grid->nx);
+            const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
+            const int span = (int)std::ceil(d) + 3;
+            const int nst = ((2 * span + 8) + 7) & ~7;
+            const int slot = nst + span + 8;
+            if (nst + span > 511) continue;
+            const size_t lds = das_lds_bytes(slot, acq->n_tx);
+            if (lds > 65536) continue;
+            const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
+            const double wgs = (double)ntz * ntx * acq->n_frames;
+            // pixels served per staged sample, discounted when the grid is
+            // too small to fill the chip
+            const double reuse = (double)ez * ex / nst;
+            const double score = reuse * std::min(1.0, wgs / 512.0);
+            if (score > best_score) {
+                best_score = score;
+                best->px = px;
+                best->tz_log2 = tzl;
+                best->span = span;
+                best->nst = nst;
+                best->slot = slot;
+                best->lds = lds;
+                best->ntz = ntz;
+                best->ntx = ntx;
+            }
+        }
+    }
+    return best_score > 0.0;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+wf_status das_common(int mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                     const int32_t* tx_elem, const double* angles, int32_t tref,
+                     const wf_grid* grid, float* out, void* stream) {
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    if (st != WF_OK) return st;
+    if (!rf) return fail(WF_ERR_INVALID_ARG, "rf is NULL");
+    if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
+    if (((uintptr_t)rf & 15) != 0) return fail(WF_ERR_UNSUPPORTED, "rf is not 16-byte aligned");
+    if (((uintptr_t)out & 3) != 0) return fail(WF_ERR_INVALID_ARG, "out is not 4-byte aligned");
+    const size_t esz = acq->dtype == WF_RF_F32 ? 4 : 2;
+    const size_t rf_bytes = (size_t)acq->n_frames * acq->n_tx * acq->n_ch * acq->n_s * esz;
+    const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
+    if (overlaps(rf, rf_bytes, out, out_bytes))
+        return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
+    Geometry g;
+    CacheEntry ce;
+    st = device_tables(mode, probe, acq, tx_elem, angles, tref, grid, &g, &ce);
+    if (st != WF_OK) return st;
+    TilePlan tp;
+    if (!choose_tile(g, acq, grid, &tp))
+        return fail(WF_ERR_UNSUPPORTED,
+                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
+                    g.dzs, g.dxs);
+    if ((long long)tp.ntz * tp.ntx > 0x7FFFFFFF)
+        return fail(WF_ERR_UNSUPPORTED, "too many tiles");
+    wf::DasArgs a{};
+    a.rf = rf;
+    a.out = out;
+    a.F = acq->n_frames;
+    a.T = acq->n_tx;
+    a.C = acq->n_ch;
+    a.S = acq->n_s;
+    a.nz = grid->nz;
+    a.nx = grid->nx;
+    a.tz_log2 = tp.tz_log2;
+    a.ntz = tp.ntz;
+    a.ntx = tp.ntx;
+    a.ng = tp.nst / 8;
+    a.ng_inv = ((1 << 20) + a.ng - 1) / a.ng;
+    a.nst = tp.nst;
+    a.slot = tp.slot;
+    a.txspan_q = (uint32_t)tp.span << wf::kQBits;
+    a.rxspan_q = (uint32_t)tp.span << wf::kQBits;
+    a.Z0 = g.Z0;
+    a.dZ = g.dZ;
+    a.dX = g.dX;
+    a.O = g.O;
+    a.fnum2 = g.fnum2;
+    a.x0f = g.x0f;
+    a.dxf = g.dxf;
+    a.tx_tab = ce.tx;
+    a.ch_tab = ce.ch;
+    hipError_t e = wf::launch_das(mode, acq->dtype, tp.px, a, tp.lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "DAS kernel launch");
+    return ok();
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+wf_status check_image(const float* a, int F, int nz, int nx, const char* name) {
+    if (!a) return fail(WF_ERR_INVALID_ARG, "%s is NULL", name);
+    if (F < 1 || F > 65535) return fail(WF_ERR_INVALID_ARG, "n_frames=%d outside [1, 65535]", F);
+    if (nz < 1 || nx < 1 || nx > 65536)
+        return fail(WF_ERR_INVALID_ARG, "image %d x %d is empty or too wide", nz, nx);
+    if ((long long)nz * nx > (1LL << 28)) return fail(WF_ERR_INVALID_ARG, "image too large");
+    return WF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wf_abi_version(void) { return WF_ABI_VERSION; }
+
+const char* wf_last_error(void) { return g_err.c_str(); }
+
+wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const wf_grid* grid, float* out, void* stream) {
+    return das_common(0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, stream);
+}
+
+wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
+                     const double* angles_rad, int32_t tref, const wf_grid* grid, float* out,
+                     void* stream) {
+    return das_common(1, rf, probe, acq, nullptr, angles_rad, tref, grid, out, stream);
+}
+
+wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                    const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                    const wf_grid* grid, float* tx_hi, float* tx_lo, float* rx_hi,
+                    float* rx_lo, void* stream) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, false);
+    if (st != WF_OK) return st;
+    if (!tx_hi || !tx_lo || !rx_hi || !rx_lo)
+        return fail(WF_ERR_INVALID_ARG, "an output pointer is NULL");
+    Geometry g;
+    CacheEntry ce;
+    st = device_tables(mode, probe, acq, tx_elem, angles_rad, tref, grid, &g, &ce);
+    if (st != WF_OK) return st;
+    wf::DelayArgs a{};
+    a.tx_hi = tx_hi;
+    a.tx_lo = tx_lo;
+    a.rx_hi = rx_hi;
+    a.rx_lo = rx_lo;
+    a.T = acq->n_tx;
+    a.C = acq->n_ch;
+    a.nz = grid->nz;
+    a.nx = grid->nx;
+    a.Z0 = g.Z0;
+    a.dZ = g.dZ;
+    a.dX = g.dX;
+    a.O = g.O;
+    a.tx_tab = ce.tx;
+    a.ch_tab = ce.ch;
+    hipError_t e = wf::launch_delays(mode, a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "delay kernel launch");
+    return ok();
+}
+
+wf_status wf_envelope(const float* bf, int32_t n_frames, int32_t nz, int32_t nx, float* env,
+                      float* col_max, void* stream) {
+    wf_status st = check_image(bf, n_frames, nz, nx, "bf");
+    if (st != WF_OK) return st;
+    if (!env) return fail(WF_ERR_INVALID_ARG, "env is NULL");
+    if (!col_max) return fail(WF_ERR_INVALID_ARG, "col_max is NULL");
+    if (!is_pow2(nz) || nz < 2 || nz > 4096)
+        return fail(WF_ERR_UNSUPPORTED, "nz=%d is not a power of two in [2, 4096]", nz);
+    const size_t img = (size_t)n_frames * nz * nx * 4;
+    if (overlaps(col_max, (size_t)n_frames * nx * 4, bf, img) ||
+        overlaps(col_max, (size_t)n_frames * nx * 4, env, img))
+        return fail(WF_ERR_INVALID_ARG, "col_max overlaps an image");
+    if (env != bf && overlaps(env, img, bf, img))
+        return fail(WF_ERR_INVALID_ARG, "env partially overlaps bf");
+    hipError_t e = wf::launch_envelope(bf, n_frames, nz, nx, env, col_max, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "envelope kernel launch");
+    return ok();
+}
+
+wf_status wf_log_compress(const float* env, const float* col_max, int32_t n_frames, int32_t nz,
+                          int32_t nx, float dr_db, int32_t flags, float* out_db, void* stream) {
+    wf_status st = check_image(env, n_frames, nz, nx, "env");
+    if (st != WF_OK) return st;
+    if (!col_max) return fail(WF_ERR_INVALID_ARG, "col_max is NULL");
+    if (!out_db) return fail(WF_ERR_INVALID_ARG, "out_db is NULL");
+    if (!std::isfinite(dr_db) || dr_db <= 0.0f)
+        return fail(WF_ERR_INVALID_ARG, "dr_db must be > 0");
+    if (flags & ~WF_BMODE_OFFSET) return fail(WF_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const size_t img = (size_t)n_frames * nz * nx * 4;
+    if (out_db != env && overlaps(out_db, img, env, img))
+        return fail(WF_ERR_INVALID_ARG, "out_db partially overlaps env");
+    if (overlaps(col_max, (size_t)n_frames * nx * 4, out_db, img))
+        return fail(WF_ERR_INVALID_ARG, "col_max overlaps out_db");
+    hipError_t e = wf::launch_log_compress(env, col_max, n_frames, nz, nx, dr_db,
+                                           flags & WF_BMODE_OFFSET, out_db, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "log-compression kernel launch");
+    return ok();
+}
+
+wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx, float dr_db,
+                   int32_t flags, float* out_db, float* col_max, void* stream) {
+    wf_status st = check_image(bf, n_frames, nz, nx, "bf");
+    if (st != WF_OK) return st;
+    if (!out_db) return fail(WF_ERR_INVALID_ARG, "out_db is NULL");
+    const size_t img = (size_t)n_frames * nz * nx * 4;
+    if (overlaps(out_db, img, bf, img)) return fail(WF_ERR_INVALID_ARG, "out_db overlaps bf");
+    if (!std::isfinite(dr_db) || dr_db <= 0.0f)
+        return fail(WF_ERR_INVALID_ARG, "dr_db must be > 0");
+    if (flags & ~WF_BMODE_OFFSET) return fail(WF_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    st = wf_envelope(bf, n_frames, nz, nx, out_db, col_max, stream);
+    if (st != WF_OK) return st;
+    return wf_log_compress(out_db, col_max, n_frames, nz, nx, dr_db, flags, out_db, stream);
+}
+
+wf_status wf_geometry_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipError_t first = hipSuccess;
+    for (auto& kv : g_cache) {
+        hipError_t e = hipFree(kv.second.dev);
+        if (e != hipSuccess && first == hipSuccess) first = e;
+    }
+    g_cache.clear();
+    if (first != hipSuccess) return hip_fail(first, "hipFree(geometry table)");
+    return ok();
+}
+
+}  // extern "C"

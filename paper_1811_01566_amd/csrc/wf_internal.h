@@ -1,0 +1,76 @@
+// Internal interfaces between the C entry points (api.cpp) and the kernel
+// launchers (das.hip, envelope.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wf {
+
+// Channels staged per pass of the DAS kernel: their one-way receive delays
+// stay in registers while every transmit streams through LDS.
+constexpr int kChunk = 16;
+// Threads per DAS workgroup (4 wave64 waves).
+constexpr int kThreads = 256;
+// Fractional bits of the fixed-point window-local delays (Q9.23): the
+// fraction lines up with the float mantissa, the integer part (< 512)
+// indexes the LDS window.
+constexpr int kQBits = 23;
+
+// Per-transmit constants of a geometry, in samples (distances scaled by
+// fs / c), split into float-float pairs on the host from double.
+//   PWI:  v0 = (C0.hi, C0.lo, Az.hi, Az.lo), v1 = (Ax.hi, Ax.lo, 0, 0) with
+//         TX(iz, ix) = C0 + iz Az + ix Ax; Az.hi and Ax.hi are multiples of
+//         2^-15 so that small integer multiples of them are exact in float.
+//   STAI: v0 = (DX.hi, DX.lo, xe, 0): DX = X(column 0) - x_e, xe the element
+//         position (float, for window bounds); v1 unused.
+struct TxConst {
+    float4 v0, v1;
+};
+
+// Per-channel constants: (DX.hi, DX.lo, xe, 0), DX = X(column 0) - x_e.
+typedef float4 ChConst;
+
+struct DasArgs {
+    const void* rf;
+    float* out;
+    int F, T, C, S, nz, nx;
+    int tz_log2;        // tile depth TZ = 1 << tz_log2
+    int ntz, ntx;       // tiles along z and x
+    int ng;             // 8-sample groups staged per window (nst / 8)
+    int ng_inv;         // ceil(2^20 / ng), exact division for small numerators
+    int nst;            // staged entries per window
+    int slot;           // LDS entries per window (staged + zero pad)
+    uint32_t txspan_q;  // clamp of window-local transmit delays (Q9.23)
+    uint32_t rxspan_q;  // clamp of window-local receive delays (Q9.23)
+    float2 Z0, dZ;      // depth of row 0 and row step, samples (float-float)
+    float2 dX;          // column step, samples (float-float)
+    float2 O;           // STAI: -t0 fs added to the transmit delay
+    float fnum2;        // 2 F# (0: no apodisation)
+    float x0f, dxf;     // lateral grid in samples (float) for window bounds
+    const TxConst* tx_tab;
+    const ChConst* ch_tab;
+};
+
+struct DelayArgs {
+    float* tx_hi;
+    float* tx_lo;
+    float* rx_hi;
+    float* rx_lo;
+    int T, C, nz, nx;
+    float2 Z0, dZ, dX, O;
+    const TxConst* tx_tab;
+    const ChConst* ch_tab;
+};
+
+// Launchers; return the hipError_t of the launch.
+hipError_t launch_das(int mode, int dtype, int px, const DasArgs& a, size_t lds_bytes,
+                      hipStream_t s);
+hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
+hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,
+                           hipStream_t s);
+hipError_t launch_log_compress(const float* env, const float* col_max, int F, int nz, int nx,
+                               float dr_db, int offset, float* out, hipStream_t s);
+
+}  // namespace wf

@@ -229,7 +229,21 @@ def _cache_path(w: Workload, tag: str) -> Optional[str]:
     return os.path.join(root, f"{w.name}_{tag}_{key}.npy")
 
 
+def _gpu_initialised() -> bool:
+    import sys
+
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:  # pragma: no cover
+        return True
+
+
 def default_workers() -> int:
+    """Worker processes for synthesis: up to 16, and none once this process
+    has initialised a GPU (worker pools are only forked from clean processes)."""
+    if _gpu_initialised():
+        return 1
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
@@ -250,7 +264,7 @@ def synth_rf(w: Workload, quantize: bool = True, workers: Optional[int] = None,
     path = _cache_path(w, tag + "_" + "-".join(map(str, frames))) if cache else None
     if path and os.path.exists(path):
         return np.load(path, allow_pickle=False)
-    workers = default_workers() if workers is None else workers
+    workers = default_workers() if workers is None else min(workers, default_workers())
     out = []
     for f in frames:
         rf = _frame_float(w, f, workers)

@@ -13,6 +13,19 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
 
 
+def pytest_collection_finish(session):
+    """Synthesise the large phantoms with a worker pool before any GPU test
+    initialises the device (pools are never forked after that)."""
+    if not any(item.get_closest_marker("gpu") for item in session.items):
+        return
+    import phantom
+    from phantom.prepare import lighter, prepare
+
+    names = ("pwi", "stai_full", "paper_stai", "paper_pwi")
+    full = [phantom.get_workload("pwi"), phantom.get_workload("stai_full")]
+    prepare([lighter(phantom.get_workload(n)) for n in names] + full)
+
+
 @pytest.fixture(scope="session")
 def wf_gpu():
     """The HIP binding on cuda:0; fails loudly when the GPU or library is missing."""

@@ -54,8 +54,11 @@ def parse():
                                                           "paper_pwi"])
     ap.add_argument("--latency-frames", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-columns", type=int, default=48,
+    ap.add_argument("--cpu-columns", type=int, default=256,
                     help="image columns of the frame the CPU oracle computes")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB, 5 times (reference "
+                         "for the HBM byte counters), and exit")
     return ap.parse_args()
 
 
@@ -142,6 +145,16 @@ def main():
 
     import paper_1811_01566_amd as wf
     import phantom
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 5}), flush=True)
+        return
 
     w = phantom.get_workload(args.workload)
     # synthesise before the GPU is initialised (the generator forks workers)

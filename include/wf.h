@@ -176,6 +176,18 @@ wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
                    float dr_db, int32_t flags, float* out_db, float* col_max,
                    void* stream);
 
+/*
+ * Launch plan the DAS calls would use for this geometry (host only; touches
+ * no device).  info (HOST int32[10]) receives: pixels per lane, tile depth,
+ * tile width, window-local delay clamp (samples), staged window entries,
+ * LDS entries per window, LDS bytes per workgroup, tiles along z, tiles
+ * along x, channels per pass.  mode 0 = STAI, 1 = PWI.  Returns
+ * WF_ERR_UNSUPPORTED when no tile shape fits (as the DAS calls would).
+ */
+wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                           const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                           const wf_grid* grid, int32_t* info);
+
 /* Message of the last failed call on this thread ("" after success). */
 const char* wf_last_error(void);
 

@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import WfError, load
 
 __all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
-           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear"]
+           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info"]
 
 
 @dataclass(frozen=True)
@@ -191,6 +191,25 @@ def das_pwi(rf, scan: Scan, out=None, stream=None):
     if scan.mode != "pwi":
         raise ValueError("scan.mode must be 'pwi'")
     return das(scan, rf, out, stream)
+
+
+TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
+                    "chunk")
+
+
+def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:
+    """Launch plan of the DAS kernel for this geometry (host only, no GPU)."""
+    lib = load()
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, n_frames, n_s, dtype)
+    mode = 0 if scan.mode == "stai" else 1
+    tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
+    ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
+    tref = _tref(scan) if mode == 1 else 0
+    info = (ctypes.c_int32 * 10)()
+    _lib.check(lib.wf_das_tile_info(mode, probe, acq, tx, ang, tref, grid,
+                                    ctypes.cast(info, _lib.c_int32_p)), "wf_das_tile_info")
+    return dict(zip(TILE_INFO_FIELDS, list(info)))
 
 
 def delays(scan: Scan, device="cuda", stream=None):

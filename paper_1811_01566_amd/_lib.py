@@ -49,6 +49,8 @@ SIGNATURES = {
     "wf_das_pwi": (I, [V, P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), V, V]),
     "wf_delays": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V, V, V,
                       V]),
+    "wf_das_tile_info": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid),
+                             c_int32_p]),
     "wf_envelope": (I, [V, I, I, I, V, V, V]),
     "wf_log_compress": (I, [V, V, I, I, I, F, I, V, V]),
     "wf_bmode": (I, [V, I, I, I, F, I, V, V, V]),

@@ -255,13 +255,20 @@ struct TilePlan {
 };
 
 size_t das_lds_bytes(int slot, int T) {
-    return (size_t)wf::kChunk * slot * 8 + (size_t)((T * 4 + 15) & ~15) + (size_t)T * 8 +
-           (size_t)wf::kChunk * 4;
+    // two window buffers, per-transmit bases, PWI per-tile bases, chunk tables
+    return 2 * (size_t)wf::kChunk * slot * 8 + (size_t)((T * 4 + 15) & ~15) + (size_t)T * 8 +
+           (size_t)wf::kChunk * 8;
 }
 
+// LDS per workgroup: plans within 64 KB are preferred; gfx950 allows up to
+// 160 KB for a single workgroup, used only when no smaller plan fits.
+constexpr size_t kLdsSoft = 65536;
+constexpr size_t kLdsHard = 163840;
+
 bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
-    double best_score = -1.0;
-    for (int px : {4, 1}) {
+    for (size_t limit : {kLdsSoft, kLdsHard}) {
+        double best_score = -1.0;
+        for (int px : {4, 1}) {
         for (int tzl = 6; tzl >= 3; --tzl) {
             const int tz = 1 << tzl;
             const int txw = (wf::kThreads * px) >> tzl;
@@ -271,8 +278,9 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
             const int nst = ((2 * span + 8) + 7) & ~7;
             const int slot = nst + span + 8;
             if (nst + span > 511) continue;
+            if (wf::kChunk * (nst / 8) > wf::kMaxGroups * wf::kThreads) continue;
             const size_t lds = das_lds_bytes(slot, acq->n_tx);
-            if (lds > 65536) continue;
+            if (lds > limit) continue;
             const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
             const double wgs = (double)ntz * ntx * acq->n_frames;
             // pixels served per staged sample, discounted when the grid is
@@ -291,8 +299,10 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
                 best->ntx = ntx;
             }
         }
+        }
+        if (best_score > 0.0) return true;
     }
-    return best_score > 0.0;
+    return false;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -353,7 +363,9 @@ wf_status das_common(int mode, const void* rf, const wf_probe* probe, const wf_a
     a.dxf = g.dxf;
     a.tx_tab = ce.tx;
     a.ch_tab = ce.ch;
-    hipError_t e = wf::launch_das(mode, acq->dtype, tp.px, a, tp.lds, (hipStream_t)stream);
+    const int groups = (wf::kChunk * a.ng + wf::kThreads - 1) / wf::kThreads;
+    hipError_t e =
+        wf::launch_das(mode, acq->dtype, tp.px, groups, a, tp.lds, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "DAS kernel launch");
     return ok();
 }
@@ -386,6 +398,33 @@ wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid, float* out,
                      void* stream) {
     return das_common(1, rf, probe, acq, nullptr, angles_rad, tref, grid, out, stream);
+}
+
+wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                           const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                           const wf_grid* grid, int32_t* info) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, true);
+    if (st != WF_OK) return st;
+    if (!info) return fail(WF_ERR_INVALID_ARG, "info is NULL");
+    Geometry g;
+    build_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, &g);
+    TilePlan tp;
+    if (!choose_tile(g, acq, grid, &tp))
+        return fail(WF_ERR_UNSUPPORTED,
+                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
+                    g.dzs, g.dxs);
+    info[0] = tp.px;
+    info[1] = 1 << tp.tz_log2;
+    info[2] = (wf::kThreads * tp.px) >> tp.tz_log2;
+    info[3] = tp.span;
+    info[4] = tp.nst;
+    info[5] = tp.slot;
+    info[6] = (int32_t)tp.lds;
+    info[7] = tp.ntz;
+    info[8] = tp.ntx;
+    info[9] = wf::kChunk;
+    return ok();
 }
 
 wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,

@@ -40,6 +40,7 @@ namespace {
 
 constexpr float kQScale = 8388608.0f;  // 2^23
 constexpr float kHiQuant = 32768.0f;   // 2^15: grid of the exact "hi" parts
+constexpr int kJB = 2;                 // channels per batch of LDS reads
 
 // ---------------------------------------------------------------------------
 // RF sample loaders: 8 consecutive samples from a 16-byte aligned address.
@@ -105,6 +106,29 @@ __device__ __forceinline__ uint32_t to_q(ff v, int base) {
     return (uint32_t)h + (uint32_t)(int)l;
 }
 
+// Window-local distance round((sqrt(dx^2 + z2) - base) * 2^23), dx and z2
+// float-float.  The square root is the hardware estimate s plus one Newton
+// correction; s - base is exact (base is an integer at most s), so the
+// correction is rounded separately and added as an integer.
+__device__ __forceinline__ uint32_t dist_q(ff dx, ff z2, int base) {
+    const ff r2 = ff_add(ff_sqr(dx), z2);
+    const float s = __builtin_amdgcn_sqrtf(r2.hi);
+    const ff p = two_prod(s, s);
+    const float r = ((r2.hi - p.hi) - p.lo) + r2.lo;
+    const float corr = r * (0.5f * __builtin_amdgcn_rcpf(fmaxf(s, 1e-30f)));
+    const float h = fmaxf((s - (float)base) * kQScale, 0.0f);
+    return (uint32_t)h + (uint32_t)(int)rintf(corr * kQScale);
+}
+
+// Byte address of window entry (u >> 23) at byte offset `off`: one shift
+// and one shift-add (the compiler would otherwise emit shift, mask, add).
+__device__ __forceinline__ uint32_t entry_addr(uint32_t u, uint32_t off) {
+    const uint32_t idx = u >> kQBits;
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 3, %2" : "=v"(r) : "v"(idx), "s"(off));
+    return r;
+}
+
 // Smallest distance (samples) from an element at (xe, 0) to the rectangle
 // [xlo, xhi] x [zlo, zhi]; plain float, used only for window bases that
 // carry a one-sample margin.
@@ -118,15 +142,86 @@ __device__ __forceinline__ float rect_min_dist(float xe, float xlo, float xhi, f
 // ---------------------------------------------------------------------------
 // K2: gather / interpolate / accumulate
 // ---------------------------------------------------------------------------
-template <int MODE, typename RT, int PX>
+
+// Raw RF of one staged group (8 samples + the next one), held in registers
+// between the global load and the LDS commit so that the load latency hides
+// behind the previous transmit's arithmetic.
+template <typename RT>
+struct RawGroup;
+
+template <>
+struct RawGroup<int16_t> {
+    int4 q;
+    int nx;
+    __device__ __forceinline__ void load(const int16_t* p, bool next) {
+        q = *reinterpret_cast<const int4*>(p);
+        nx = next ? (int)p[8] : 0;
+    }
+    __device__ __forceinline__ void zero() { q = make_int4(0, 0, 0, 0); nx = 0; }
+    __device__ __forceinline__ void get(float v[9]) const {
+        const int w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = (float)((w[i] << 16) >> 16);
+            v[2 * i + 1] = (float)(w[i] >> 16);
+        }
+        v[8] = (float)nx;
+    }
+};
+
+template <>
+struct RawGroup<__half> {
+    int4 q;
+    float nx;
+    __device__ __forceinline__ void load(const __half* p, bool next) {
+        q = *reinterpret_cast<const int4*>(p);
+        nx = next ? __half2float(p[8]) : 0.0f;
+    }
+    __device__ __forceinline__ void zero() { q = make_int4(0, 0, 0, 0); nx = 0.0f; }
+    __device__ __forceinline__ void get(float v[9]) const {
+        const int w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            __half_raw lo, hi;
+            lo.x = (unsigned short)(w[i] & 0xFFFF);
+            hi.x = (unsigned short)((unsigned)w[i] >> 16);
+            v[2 * i] = __half2float(__half(lo));
+            v[2 * i + 1] = __half2float(__half(hi));
+        }
+        v[8] = nx;
+    }
+};
+
+template <>
+struct RawGroup<float> {
+    float4 a, b;
+    float nx;
+    __device__ __forceinline__ void load(const float* p, bool next) {
+        a = *reinterpret_cast<const float4*>(p);
+        b = *reinterpret_cast<const float4*>(p + 4);
+        nx = next ? p[8] : 0.0f;
+    }
+    __device__ __forceinline__ void zero() {
+        a = make_float4(0, 0, 0, 0);
+        b = a;
+        nx = 0.0f;
+    }
+    __device__ __forceinline__ void get(float v[9]) const {
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        v[8] = nx;
+    }
+};
+
+template <int MODE, typename RT, int PX, int NG>
 __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
-    float2* win = reinterpret_cast<float2*>(smem);
-    const size_t win_bytes = (size_t)kChunk * slot * sizeof(float2);
-    int* a_tab = reinterpret_cast<int*>(smem + win_bytes);
-    float2* p_tab = reinterpret_cast<float2*>(smem + win_bytes + ((a.T * 4 + 15) & ~15));
+    const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
+    float2* win = reinterpret_cast<float2*>(smem);  // two buffers of kChunk windows
+    int* a_tab = reinterpret_cast<int*>(smem + 2 * buf_bytes);
+    float2* p_tab = reinterpret_cast<float2*>(smem + 2 * buf_bytes + ((a.T * 4 + 15) & ~15));
     int* b_tab = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(p_tab) + a.T * 8);
 
     const int frame = blockIdx.y;
@@ -169,10 +264,10 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         }
         a_tab[t] = at;
     }
-    // zero pad behind every window (never overwritten by staging)
+    // zero pad behind every window of both buffers (never overwritten)
     {
         const int pad = slot - a.nst;
-        for (int i = tid; i < kChunk * pad; i += kThreads) {
+        for (int i = tid; i < 2 * kChunk * pad; i += kThreads) {
             const int j = i / pad;
             win[j * slot + a.nst + (i - j * pad)] = make_float2(0.0f, 0.0f);
         }
@@ -200,20 +295,112 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         acc[k] = 0.0f;
     }
     const uint32_t masked = (uint32_t)a.nst << kQBits;
+    const float kstep = (float)(kThreads >> a.tz_log2);  // columns between a lane's pixels
     const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame * a.T * a.C * a.S;
+    const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * 256)
 
     for (int c0 = 0; c0 < a.C; c0 += kChunk) {
         __syncthreads();  // previous chunk's readers of b_tab / windows are done
         if (tid < kChunk) {
             const int c = c0 + tid;
-            int b = 0;
-            if (c < a.C) b = (int)floorf(rect_min_dist(a.ch_tab[c].z, xlo, xhi, zlo, zhi)) - 1;
+            int b = 0, act = 0;
+            if (c < a.C) {
+                const float xe = a.ch_tab[c].z;
+                b = (int)floorf(rect_min_dist(xe, xlo, xhi, zlo, zhi)) - 1;
+                // does the receive aperture of this channel reach any pixel
+                // of the tile?  (one sample of margin)
+                const float dxm = fmaxf(0.0f, fmaxf(xlo - xe, xe - xhi));
+                act = !(a.fnum2 > 0.0f) || (a.fnum2 * dxm <= zhi + 1.0f);
+            }
             b_tab[tid] = b;
+            b_tab[kChunk + tid] = act;
         }
         __syncthreads();
         int bj[kChunk];
+        int any_act = 0, bmin = 0x7fffffff, bmax = -0x7fffffff;
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) bj[j] = __builtin_amdgcn_readfirstlane(b_tab[j]);
+        for (int j = 0; j < kChunk; ++j) {
+            bj[j] = __builtin_amdgcn_readfirstlane(b_tab[j]);
+            any_act |= __builtin_amdgcn_readfirstlane(b_tab[kChunk + j]);
+            bmin = min(bmin, bj[j]);
+            bmax = max(bmax, bj[j]);
+        }
+        if (!any_act) continue;  // the whole chunk is outside the tile's aperture
+
+        // a transmit pass whose windows all lie outside the record adds nothing
+        auto next_active = [&](int t) {
+            for (; t < a.T; ++t) {
+                const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+                if (!(at + bmin > a.S - 2 || at + bmax + a.nst < 0)) break;
+            }
+            return t;
+        };
+
+        // global -> registers for pass t (nothing written yet)
+        RawGroup<RT> raw[NG];
+        auto issue = [&](int t) {
+            const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+            const RT* rf_t = rf_frame + (size_t)t * a.C * a.S;
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                const int w = tid + gi * kThreads;
+                if (w < ngroups) {
+                    const int j = (w * a.ng_inv) >> 20;
+                    const int g = w - j * a.ng;
+                    const int c = c0 + j;
+                    const int s0 = ((at + b_tab[j]) & ~7) + 8 * g;
+                    if (c < a.C && s0 >= 0 && s0 + 8 <= a.S)
+                        raw[gi].load(rf_t + (size_t)c * a.S + s0, s0 + 8 <= a.S - 1);
+                    else
+                        raw[gi].zero();
+                }
+            }
+        };
+        // registers -> interpolation pairs in LDS buffer `buf`
+        auto commit = [&](int t, int buf) {
+            const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                const int w = tid + gi * kThreads;
+                if (w < ngroups) {
+                    const int j = (w * a.ng_inv) >> 20;
+                    const int g = w - j * a.ng;
+                    const int c = c0 + j;
+                    const int s0 = ((at + b_tab[j]) & ~7) + 8 * g;
+                    float v[9];
+                    raw[gi].get(v);
+                    float4* dst =
+                        reinterpret_cast<float4*>(win + (buf * kChunk + j) * slot + 8 * g);
+                    if (c < a.C && s0 >= 0 && s0 + 8 <= a.S - 1) {
+                        // whole group inside the record: every pair is valid
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            dst[i] = make_float4(fmaf(2.0f, v[2 * i], -v[2 * i + 1]),
+                                                 v[2 * i + 1] - v[2 * i],
+                                                 fmaf(2.0f, v[2 * i + 1], -v[2 * i + 2]),
+                                                 v[2 * i + 2] - v[2 * i + 1]);
+                    } else {
+                        // record edge or outside: pairs with n < 0 or n > S-2 are 0
+                        const bool inr = (c < a.C) && (s0 >= 0) && (s0 + 8 <= a.S);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float e[2], d[2];
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int m = 2 * i + h;
+                                const bool ok = inr && (s0 + m <= a.S - 2);
+                                e[h] = ok ? fmaf(2.0f, v[m], -v[m + 1]) : 0.0f;
+                                d[h] = ok ? (v[m + 1] - v[m]) : 0.0f;
+                            }
+                            dst[i] = make_float4(e[0], d[0], e[1], d[1]);
+                        }
+                    }
+                }
+            }
+        };
+
+        int t = next_active(0);
+        if (t >= a.T) continue;  // no transmit reaches this tile through this chunk
 
         // receive delays of this chunk, window-local Q9.23
         uint32_t rq[PX][kChunk];
@@ -227,7 +414,7 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
                     const ff d = ff_add(ff_make(cc.x, cc.y), ixdx[k]);
                     const bool on =
                         valid[k] && !(a.fnum2 > 0.0f && a.fnum2 * fabsf(d.hi) > zp[k].hi);
-                    const uint32_t q = min(to_q(dist_ff(d, z2[k]), bj[j]), a.rxspan_q);
+                    const uint32_t q = min(dist_q(d, z2[k], bj[j]), a.rxspan_q);
                     rq[k][j] = on ? q : masked;
                 }
             } else {
@@ -236,22 +423,35 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
             }
         }
 
-        for (int t = 0; t < a.T; ++t) {
+        // software pipeline over transmit passes, two LDS buffers: commit
+        // pass t into buffer `cur` (last read two passes ago, before the
+        // barrier of the previous iteration), barrier, then issue the loads
+        // of the next pass so that they fly while pass t is accumulated
+        issue(t);
+        int cur = 0;
+        while (t < a.T) {
+            const int tn = next_active(t + 1);
+            commit(t, cur);
+            __syncthreads();
+            if (tn < a.T) issue(tn);
             const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+
             uint32_t tq[PX];
             if (MODE == 1) {
                 const float2 pb = p_tab[t];
                 const TxConst tc = a.tx_tab[t];
                 const float azh = tc.v0.z * kQScale, azl = tc.v0.w * kQScale;
                 const float axh = tc.v1.x * kQScale, axl = tc.v1.y * kQScale;
+                // exact: every term is a multiple of 2^8 below 2^32
+                const float s = fmaf(qz[0], azh, fmaf(qx[0], axh, pb.x));
+                const float l = fmaf(qz[0], azl, fmaf(qx[0], axl, pb.y));
+                const uint32_t q0 = (uint32_t)fmaxf(s, 0.0f) + (uint32_t)(int)rintf(l);
+                // a lane's pixels are kstep columns apart: the delay grows by
+                // the same Q9.23 step (rounded once; <= 1.5 units of error)
+                const int dq =
+                    __builtin_amdgcn_readfirstlane((int)rintf(fmaf(kstep, axh, kstep * axl)));
 #pragma unroll
-                for (int k = 0; k < PX; ++k) {
-                    // exact: every term is a multiple of 2^8 below 2^32
-                    const float s = fmaf(qz[k], azh, fmaf(qx[k], axh, pb.x));
-                    const float l = fmaf(qz[k], azl, fmaf(qx[k], axl, pb.y));
-                    const uint32_t q = (uint32_t)fmaxf(s, 0.0f) + (uint32_t)(int)rintf(l);
-                    tq[k] = min(q, a.txspan_q);
-                }
+                for (int k = 0; k < PX; ++k) tq[k] = min(q0 + (uint32_t)(k * dq), a.txspan_q);
             } else {
                 const TxConst tc = a.tx_tab[t];
 #pragma unroll
@@ -262,59 +462,35 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
                 }
             }
 
-            __syncthreads();  // everyone is done reading the previous windows
-            // ---- stage windows (t, c0 .. c0+15) into LDS ------------------
-            {
-                const RT* rf_t = rf_frame + (size_t)t * a.C * a.S;
-                for (int w = tid; w < kChunk * a.ng; w += kThreads) {
-                    const int j = (w * a.ng_inv) >> 20;
-                    const int g = w - j * a.ng;
-                    const int c = c0 + j;
-                    const int n0 = at + b_tab[j];
-                    const int s0 = (n0 & ~7) + 8 * g;
-                    float v[8];
-                    float nxt = 0.0f;
-                    const bool inr = (c < a.C) && (s0 >= 0) && (s0 + 8 <= a.S);
-                    if (inr) {
-                        const RT* row = rf_t + (size_t)c * a.S;
-                        RfLoad<RT>::load8(row + s0, v);
-                        if (s0 + 8 <= a.S - 1) nxt = RfLoad<RT>::load1(row + s0 + 8);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) v[i] = 0.0f;
-                    }
-                    float4* dst = reinterpret_cast<float4*>(win + j * slot + 8 * g);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float e[2], d[2];
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int m = 2 * i + h;
-                            const float r0 = v[m];
-                            const float r1 = (m < 7) ? v[m + 1] : nxt;
-                            const bool ok = inr && (s0 + m <= a.S - 2);
-                            e[h] = ok ? fmaf(2.0f, r0, -r1) : 0.0f;
-                            d[h] = ok ? (r1 - r0) : 0.0f;
-                        }
-                        dst[i] = make_float4(e[0], d[0], e[1], d[1]);
-                    }
-                }
-            }
-            __syncthreads();
-
             // ---- gather / interpolate / accumulate -------------------------
+            // batches of LDS reads are issued before their FMAs so that
+            // several reads are in flight per wave
+            const uint32_t base = (uint32_t)cur * buf_bytes;
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const uint32_t off = (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+            for (int j0 = 0; j0 < kChunk; j0 += kJB) {
+                float2 ed[kJB][PX];
+                float f1[kJB][PX];
 #pragma unroll
-                for (int k = 0; k < PX; ++k) {
-                    const uint32_t u = tq[k] + rq[k][j];
-                    const uint32_t idx = u >> kQBits;
-                    const float f1 = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
-                    const float2 ed = *reinterpret_cast<const float2*>(smem + off + idx * 8u);
-                    acc[k] += fmaf(f1, ed.y, ed.x);
+                for (int jj = 0; jj < kJB; ++jj) {
+                    const int j = j0 + jj;
+                    const uint32_t off =
+                        base + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+#pragma unroll
+                    for (int k = 0; k < PX; ++k) {
+                        const uint32_t u = tq[k] + rq[k][j];
+                        f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
+                        ed[jj][k] = *reinterpret_cast<const float2*>(smem + entry_addr(u, off));
+                    }
                 }
+#pragma unroll
+                for (int jj = 0; jj < kJB; ++jj)
+#pragma unroll
+                    for (int k = 0; k < PX; ++k)
+                        acc[k] += fmaf(f1[jj][k], ed[jj][k].y, ed[jj][k].x);
             }
+
+            cur ^= 1;
+            t = tn;
         }
     }
 
@@ -357,33 +533,48 @@ __global__ void __launch_bounds__(256) delays_kernel(const DelayArgs a) {
     }
 }
 
-template <int MODE, typename RT>
-hipError_t launch_px(int px, const DasArgs& a, size_t lds, hipStream_t s) {
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int MODE, typename RT, int PX, int NG>
+hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(das_kernel<MODE, RT, PX, NG>, lds);
+    if (e != hipSuccess) return e;
     dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F);
-    dim3 block(kThreads);
-    if (px == 4) {
-        hipLaunchKernelGGL((das_kernel<MODE, RT, 4>), grid, block, lds, s, a);
-    } else {
-        hipLaunchKernelGGL((das_kernel<MODE, RT, 1>), grid, block, lds, s, a);
-    }
+    hipLaunchKernelGGL((das_kernel<MODE, RT, PX, NG>), grid, dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
 
+template <int MODE, typename RT>
+hipError_t launch_px(int px, int groups, const DasArgs& a, size_t lds, hipStream_t s) {
+    if (px == 4)
+        return groups <= 2 ? launch_one<MODE, RT, 4, 2>(a, lds, s)
+                           : launch_one<MODE, RT, 4, 4>(a, lds, s);
+    return groups <= 2 ? launch_one<MODE, RT, 1, 2>(a, lds, s)
+                       : launch_one<MODE, RT, 1, 4>(a, lds, s);
+}
+
 template <int MODE>
-hipError_t launch_mode(int dtype, int px, const DasArgs& a, size_t lds, hipStream_t s) {
+hipError_t launch_mode(int dtype, int px, int groups, const DasArgs& a, size_t lds,
+                       hipStream_t s) {
     switch (dtype) {
-        case 0: return launch_px<MODE, int16_t>(px, a, lds, s);
-        case 1: return launch_px<MODE, __half>(px, a, lds, s);
-        default: return launch_px<MODE, float>(px, a, lds, s);
+        case 0: return launch_px<MODE, int16_t>(px, groups, a, lds, s);
+        case 1: return launch_px<MODE, __half>(px, groups, a, lds, s);
+        default: return launch_px<MODE, float>(px, groups, a, lds, s);
     }
 }
 
 }  // namespace
 
-hipError_t launch_das(int mode, int dtype, int px, const DasArgs& a, size_t lds_bytes,
-                      hipStream_t s) {
-    return mode == 1 ? launch_mode<1>(dtype, px, a, lds_bytes, s)
-                     : launch_mode<0>(dtype, px, a, lds_bytes, s);
+hipError_t launch_das(int mode, int dtype, int px, int groups, const DasArgs& a,
+                      size_t lds_bytes, hipStream_t s) {
+    if (groups > kMaxGroups) return hipErrorInvalidValue;
+    return mode == 1 ? launch_mode<1>(dtype, px, groups, a, lds_bytes, s)
+                     : launch_mode<0>(dtype, px, groups, a, lds_bytes, s);
 }
 
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s) {

@@ -13,6 +13,10 @@ namespace wf {
 constexpr int kChunk = 16;
 // Threads per DAS workgroup (4 wave64 waves).
 constexpr int kThreads = 256;
+// Staged 8-sample RF groups per lane and transmit pass: the kernel is built
+// for 2 or 4 (register staging), the launch plan picks the smaller that
+// covers kChunk * groups-per-window.
+constexpr int kMaxGroups = 4;
 // Fractional bits of the fixed-point window-local delays (Q9.23): the
 // fraction lines up with the float mantissa, the integer part (< 512)
 // indexes the LDS window.
@@ -65,8 +69,8 @@ struct DelayArgs {
 };
 
 // Launchers; return the hipError_t of the launch.
-hipError_t launch_das(int mode, int dtype, int px, const DasArgs& a, size_t lds_bytes,
-                      hipStream_t s);
+hipError_t launch_das(int mode, int dtype, int px, int groups, const DasArgs& a,
+                      size_t lds_bytes, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
 hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,
                            hipStream_t s);

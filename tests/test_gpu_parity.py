@@ -42,10 +42,13 @@ def _gpu(a, dtype=None):
 
 
 def _run_das(wf, w, rf_np, torch_dtype=None):
+    """DAS of rf [F][T][C][S] or [T][C][S]; always returns [F][nz][nx]."""
     torch = _torch()
+    rf_np = rf_np if rf_np.ndim == 4 else rf_np[None]
     rf = _gpu(rf_np, torch_dtype)
     y = wf.das(scan_from_workload(w), rf)
     torch.cuda.synchronize()
+    assert y.dim() == 3
     return y.cpu().numpy().astype(np.float64)
 
 

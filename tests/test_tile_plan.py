@@ -1,0 +1,55 @@
+"""DAS launch plans (host only): the LDS window invariants that keep every
+index of the kernel inside its buffers hold for every workload shape."""
+
+import pytest
+
+import paper_1811_01566_amd as wf
+import phantom
+from phantom.configs import served_mix
+from wfhelp import scan_from_workload
+
+QMAX = 511  # Q9.23: window-local delay sums stay below 512 samples
+LDS_LIMIT = 163840  # gfx950: up to 160 KB of LDS for one workgroup
+THREADS = 256
+
+
+def _check(w):
+    info = wf.tile_info(scan_from_workload(w), w.n_s, w.n_frames)
+    span, nst, slot = info["span"], info["nst"], info["slot"]
+    # unmasked: entry (n0 & 7) + floor(tx + rx) <= 7 + 2 span < nst
+    assert 7 + 2 * span < nst
+    # masked: receive delay = nst, entry <= 7 + nst + span < slot
+    assert 7 + nst + span < slot
+    assert nst + span <= QMAX
+    assert nst % 8 == 0
+    assert info["lds_bytes"] <= LDS_LIMIT
+    assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 12 * w.n_tx
+    # staged groups of one pass fit the per-lane register staging
+    assert info["chunk"] * (nst // 8) <= 4 * THREADS
+    assert info["tile_z"] * info["tile_x"] == THREADS * info["px"]
+    assert THREADS % info["tile_z"] == 0
+    assert info["ntz"] * info["tile_z"] >= w.nz > (info["ntz"] - 1) * info["tile_z"]
+    assert info["ntx"] * info["tile_x"] >= w.nx > (info["ntx"] - 1) * info["tile_x"]
+    return info
+
+
+@pytest.mark.parametrize("name", ["stai_small", "stai_full", "pwi", "pwi_batch8", "paper_stai",
+                                  "paper_pwi"])
+def test_named_workloads(name):
+    info = _check(phantom.get_workload(name))
+    if name == "pwi":
+        assert info["px"] == 4 and info["tile_z"] == 64
+
+
+def test_tiny_and_edge_workloads():
+    for w in (phantom.tiny_stai(), phantom.tiny_pwi(), phantom.tiny_pwi(nz=1, nx=1),
+              phantom.tiny_stai(f_number=0.8, t0=0.3e-6)):
+        _check(w)
+
+
+def test_served_mix_shapes():
+    n = 0
+    for w in served_mix():
+        _check(w)
+        n += 1
+    assert n == 207  # 23 (mode, N, T) combinations x 3 record lengths x 3 grids

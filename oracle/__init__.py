@@ -41,6 +41,12 @@ from .das import (
     das_workload,
     workload_tof,
 )
+from .adjoint import (
+    das_adjoint_sum,
+    das_dydc_sum,
+    das_adjoint_workload,
+    das_dydc_workload,
+)
 from .analytic import hilbert_multiplier, analytic_signal, envelope
 from .dbclip import log_compress, bmode
 
@@ -49,4 +55,5 @@ __all__ = [
     "tof_pwi_transmit", "pwi_time_offset", "fractional_index", "interp_linear",
     "receive_weight", "das_sum", "das_stai", "das_pwi", "das_workload", "workload_tof",
     "hilbert_multiplier", "analytic_signal", "envelope", "log_compress", "bmode",
+    "das_adjoint_sum", "das_dydc_sum", "das_adjoint_workload", "das_dydc_workload",
 ]

@@ -255,9 +255,8 @@ struct TilePlan {
 };
 
 size_t das_lds_bytes(int slot, int T) {
-    // two window buffers, per-transmit bases, PWI per-tile bases, chunk tables
-    return 2 * (size_t)wf::kChunk * slot * 8 + (size_t)((T * 4 + 15) & ~15) + (size_t)T * 8 +
-           (size_t)wf::kChunk * 8;
+    // two window buffers, two 16-byte per-transmit tables, chunk tables
+    return 2 * (size_t)wf::kChunk * slot * 8 + (size_t)T * 32 + (size_t)wf::kChunk * 8;
 }
 
 // LDS per workgroup: plans within 64 KB are preferred; gfx950 allows up to

@@ -120,6 +120,8 @@ __device__ __forceinline__ uint32_t dist_q(ff dx, ff z2, int base) {
     return (uint32_t)h + (uint32_t)(int)rintf(corr * kQScale);
 }
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+
 // Byte address of window entry (u >> 23) at byte offset `off`: one shift
 // and one shift-add (the compiler would otherwise emit shift, mask, add).
 __device__ __forceinline__ uint32_t entry_addr(uint32_t u, uint32_t off) {
@@ -220,9 +222,13 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
     const int slot = a.slot;
     const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
     float2* win = reinterpret_cast<float2*>(smem);  // two buffers of kChunk windows
-    int* a_tab = reinterpret_cast<int*>(smem + 2 * buf_bytes);
-    float2* p_tab = reinterpret_cast<float2*>(smem + 2 * buf_bytes + ((a.T * 4 + 15) & ~15));
-    int* b_tab = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(p_tab) + a.T * 8);
+    // per transmit: (window base a_t, PWI column step, PWI tile base hi, lo)
+    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * buf_bytes);
+    // per transmit: PWI (Az.hi, Az.lo, Ax.hi, Ax.lo) * 2^23; STAI (DX.hi, DX.lo, xe, 0)
+    float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
+    int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
+    // LDS byte offset of the window buffers (folded into scalar offsets)
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
     const int frame = blockIdx.y;
     const int tile = blockIdx.x;
@@ -241,10 +247,13 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
     const float zlo = fminf(za, zb), zhi = fmaxf(za, zb);
     const float xlo = fminf(xa, xb), xhi = fmaxf(xa, xb);
 
-    // ---- per-transmit window bases for this tile --------------------------
+    // ---- per-transmit window bases and constants for this tile -------------
+    const float kstep = (float)(kThreads >> a.tz_log2);  // columns between a lane's pixels
     for (int t = tid; t < a.T; t += kThreads) {
         const TxConst tc = a.tx_tab[t];
-        int at;
+        int at, dq = 0;
+        float2 pb = make_float2(0.0f, 0.0f);
+        float4 q;
         if (MODE == 1) {
             const float c0 = tc.v0.x, az = tc.v0.z, ax = tc.v1.x;
             const float m00 = c0 + (float)iz0 * az + (float)ix0 * ax;
@@ -258,11 +267,18 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
             base = ff_add_f(base, -(float)at);
             const float bh = rintf(base.hi * kHiQuant) * (1.0f / kHiQuant);
             const float bl = (base.hi - bh) + base.lo;
-            p_tab[t] = make_float2(bh * kQScale, bl * kQScale);
+            pb = make_float2(bh * kQScale, bl * kQScale);
+            q = make_float4(tc.v0.z * kQScale, tc.v0.w * kQScale, tc.v1.x * kQScale,
+                            tc.v1.y * kQScale);
+            // a lane's pixels are kstep columns apart: the delay grows by the
+            // same Q9.23 step (rounded once; <= 1.5 units of error)
+            dq = (int)rintf(fmaf(kstep, q.z, kstep * q.w));
         } else {
             at = (int)floorf(rect_min_dist(tc.v0.z, xlo, xhi, zlo, zhi) + a.O.x) - 1;
+            q = tc.v0;
         }
-        a_tab[t] = at;
+        m_tab[t] = make_int4(at, dq, __float_as_int(pb.x), __float_as_int(pb.y));
+        q_tab[t] = q;
     }
     // zero pad behind every window of both buffers (never overwritten)
     {
@@ -295,7 +311,6 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         acc[k] = 0.0f;
     }
     const uint32_t masked = (uint32_t)a.nst << kQBits;
-    const float kstep = (float)(kThreads >> a.tz_log2);  // columns between a lane's pixels
     const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame * a.T * a.C * a.S;
     const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * 256)
 
@@ -330,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         // a transmit pass whose windows all lie outside the record adds nothing
         auto next_active = [&](int t) {
             for (; t < a.T; ++t) {
-                const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+                const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
                 if (!(at + bmin > a.S - 2 || at + bmax + a.nst < 0)) break;
             }
             return t;
@@ -339,7 +354,7 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         // global -> registers for pass t (nothing written yet)
         RawGroup<RT> raw[NG];
         auto issue = [&](int t) {
-            const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
             const RT* rf_t = rf_frame + (size_t)t * a.C * a.S;
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
@@ -358,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
         };
         // registers -> interpolation pairs in LDS buffer `buf`
         auto commit = [&](int t, int buf) {
-            const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * kThreads;
@@ -434,29 +449,24 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
             commit(t, cur);
             __syncthreads();
             if (tn < a.T) issue(tn);
-            const int at = __builtin_amdgcn_readfirstlane(a_tab[t]);
+            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
 
             uint32_t tq[PX];
             if (MODE == 1) {
-                const float2 pb = p_tab[t];
-                const TxConst tc = a.tx_tab[t];
-                const float azh = tc.v0.z * kQScale, azl = tc.v0.w * kQScale;
-                const float axh = tc.v1.x * kQScale, axl = tc.v1.y * kQScale;
+                const int4 m = m_tab[t];
+                const float4 q = q_tab[t];
                 // exact: every term is a multiple of 2^8 below 2^32
-                const float s = fmaf(qz[0], azh, fmaf(qx[0], axh, pb.x));
-                const float l = fmaf(qz[0], azl, fmaf(qx[0], axl, pb.y));
+                const float s = fmaf(qz[0], q.x, fmaf(qx[0], q.z, __int_as_float(m.z)));
+                const float l = fmaf(qz[0], q.y, fmaf(qx[0], q.w, __int_as_float(m.w)));
                 const uint32_t q0 = (uint32_t)fmaxf(s, 0.0f) + (uint32_t)(int)rintf(l);
-                // a lane's pixels are kstep columns apart: the delay grows by
-                // the same Q9.23 step (rounded once; <= 1.5 units of error)
-                const int dq =
-                    __builtin_amdgcn_readfirstlane((int)rintf(fmaf(kstep, axh, kstep * axl)));
+                const int dq = __builtin_amdgcn_readfirstlane(m.y);
 #pragma unroll
                 for (int k = 0; k < PX; ++k) tq[k] = min(q0 + (uint32_t)(k * dq), a.txspan_q);
             } else {
-                const TxConst tc = a.tx_tab[t];
+                const float4 q = q_tab[t];
 #pragma unroll
                 for (int k = 0; k < PX; ++k) {
-                    const ff d = ff_add(ff_make(tc.v0.x, tc.v0.y), ixdx[k]);
+                    const ff d = ff_add(ff_make(q.x, q.y), ixdx[k]);
                     const ff v = ff_add(dist_ff(d, z2[k]), ff_make(a.O.x, a.O.y));
                     tq[k] = min(to_q(v, at), a.txspan_q);
                 }
@@ -465,7 +475,7 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
             // ---- gather / interpolate / accumulate -------------------------
             // batches of LDS reads are issued before their FMAs so that
             // several reads are in flight per wave
-            const uint32_t base = (uint32_t)cur * buf_bytes;
+            const uint32_t base = lds0 + (uint32_t)cur * buf_bytes;
 #pragma unroll
             for (int j0 = 0; j0 < kChunk; j0 += kJB) {
                 float2 ed[kJB][PX];
@@ -479,7 +489,9 @@ __global__ void __launch_bounds__(kThreads) das_kernel(const DasArgs a) {
                     for (int k = 0; k < PX; ++k) {
                         const uint32_t u = tq[k] + rq[k][j];
                         f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
-                        ed[jj][k] = *reinterpret_cast<const float2*>(smem + entry_addr(u, off));
+                        const v2f e2 = *reinterpret_cast<const __attribute__((address_space(3))) v2f*>(
+                            (uintptr_t)entry_addr(u, off));
+                        ed[jj][k] = make_float2(e2.x, e2.y);
                     }
                 }
 #pragma unroll

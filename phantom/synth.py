@@ -34,7 +34,7 @@ import numpy as np
 
 from .configs import Workload
 
-GEN_VERSION = 3
+GEN_VERSION = 4
 UPSAMPLE = 16
 ADC_FULL_SCALE = 8191.0
 
@@ -254,18 +254,22 @@ def default_workers() -> int:
 def synth_rf(w: Workload, quantize: bool = True, workers: Optional[int] = None,
              cache: bool = True, frames: Optional[Sequence[int]] = None) -> np.ndarray:
     """RF channel data [F][T][C][S]: int16 counts (quantize=True) or the
-    pre-quantisation float64 record in the same count units."""
+    pre-quantisation record in the same count units (float64; cached as
+    float32, i.e. to ~1e-7 relative).  One synthesis fills both caches."""
     frames = list(range(w.n_frames)) if frames is None else list(frames)
     if w.phantom == "random":
         rng = np.random.default_rng(np.random.SeedSequence([w.seed, 99]))
         r = rng.integers(-8191, 8192, size=(len(frames), w.n_tx, w.n_ch, w.n_s))
         return r.astype(np.int16 if quantize else np.float64)
-    tag = "i16" if quantize else "f64"
-    path = _cache_path(w, tag + "_" + "-".join(map(str, frames))) if cache else None
-    if path and os.path.exists(path):
-        return np.load(path, allow_pickle=False)
+    fkey = "-".join(map(str, frames))
+    p16 = _cache_path(w, "i16_" + fkey) if cache else None
+    p32 = _cache_path(w, "f32_" + fkey) if cache else None
+    want = p16 if quantize else p32
+    if want and os.path.exists(want):
+        arr = np.load(want, allow_pickle=False)
+        return arr if quantize else arr.astype(np.float64)
     workers = default_workers() if workers is None else min(workers, default_workers())
-    out = []
+    q, raw = [], []
     for f in frames:
         rf = _frame_float(w, f, workers)
         if w.snr_db is not None:
@@ -275,15 +279,16 @@ def synth_rf(w: Workload, quantize: bool = True, workers: Optional[int] = None,
         peak = float(np.max(np.abs(rf)))
         scale = ADC_FULL_SCALE / peak if peak > 0 else 1.0
         rf = rf * scale
-        if quantize:
-            rf = np.clip(np.rint(rf), -32767, 32767).astype(np.int16)
-        out.append(rf)
-    arr = np.stack(out)
-    if path:
-        tmp = path + f".tmp{os.getpid()}.npy"
-        np.save(tmp, arr)
-        os.replace(tmp, path)
-    return arr
+        q.append(np.clip(np.rint(rf), -32767, 32767).astype(np.int16))
+        raw.append(rf.astype(np.float32) if cache else rf)
+    a16 = np.stack(q)
+    a32 = np.stack(raw)
+    for path, arr in ((p16, a16), (p32, a32)):
+        if path:
+            tmp = path + f".tmp{os.getpid()}.npy"
+            np.save(tmp, arr)
+            os.replace(tmp, path)
+    return a16 if quantize else a32.astype(np.float64)
 
 
 def point_echo_rf(w: Workload, x: float, z: float, amp: complex = 1.0) -> np.ndarray:

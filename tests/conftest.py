@@ -21,7 +21,7 @@ def pytest_collection_finish(session):
     import phantom
     from phantom.prepare import lighter, prepare
 
-    names = ("pwi", "stai_full", "paper_stai", "paper_pwi")
+    names = ("pwi", "stai_full", "paper_stai", "paper_pwi", "pwi_batch8")
     full = [phantom.get_workload("pwi"), phantom.get_workload("stai_full")]
     prepare([lighter(phantom.get_workload(n)) for n in names] + full)
 

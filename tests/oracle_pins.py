@@ -20,6 +20,7 @@ import phantom
 import phantom.synth
 from oracle import dbclip as B
 from oracle import das as D
+from oracle import adjoint as A
 from oracle import analytic as E
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -341,6 +342,39 @@ def pin_bmode_per_frame_and_degenerate():
     assert np.all(np.isfinite(z))
 
 
+# --------------------------------------------------------------------------
+# derivatives (adjoint w.r.t. RF, derivative w.r.t. the speed of sound)
+# --------------------------------------------------------------------------
+
+def pin_adjoint_dot_product():
+    """<A r, g> = <r, A^T g> for the (pinned) forward A."""
+    rng = np.random.default_rng(21)
+    for w in (phantom.tiny_stai(f_number=0.8, t0=0.3e-6), phantom.tiny_pwi(f_number=1.2)):
+        r = rng.normal(size=(w.n_tx, w.n_ch, w.n_s))
+        g = rng.normal(size=(w.nz, w.nx))
+        lhs = float(np.sum(D.das_workload(r, w) * g))
+        rhs = float(np.sum(r * A.das_adjoint_workload(g, w)))
+        _close(lhs, rhs, rtol=1e-12, atol=1e-12, msg=f"adjoint dot product {w.name}")
+
+
+def pin_dydc_linear_ramp():
+    """r[s] = a + b s: y = sum (a + b u) exactly, so dy/dc = b sum du/dc with
+    du/dc = -(tau_tx + tau_rx) fs / c (times of flight are lengths over c)."""
+    a, b = 2.0, -0.375
+    for w in (_deep_stai(), phantom.tiny_pwi(n_elem=8, n_ch=8, n_s=4096, nz=5, nx=7,
+                                             z_min=4e-3, z_max=12e-3)):
+        rf = np.broadcast_to(a + b * np.arange(w.n_s, dtype=np.float64),
+                             (w.n_tx, w.n_ch, w.n_s))
+        got = A.das_dydc_workload(rf, w)
+        ttx, trx = D.workload_tof(w)
+        exp = b * sum(-(ttx[t][None] + trx).sum(axis=0) * w.fs / w.c for t in range(w.n_tx))
+        _close(got, exp, rtol=1e-10, msg=f"dy/dc ramp {w.name}")
+        # and the same against a central difference of the forward (linear in u)
+        h = 1e-3
+        fd = (D.das_workload(rf, w.with_(c=w.c + h)) - D.das_workload(rf, w.with_(c=w.c - h))) / (2 * h)
+        _close(got, fd, rtol=1e-6, msg=f"dy/dc ramp vs central difference {w.name}")
+
+
 ALL_PINS = [
     pin_tof_golden,
     pin_pwi_wavefront_geometry,
@@ -357,4 +391,6 @@ ALL_PINS = [
     pin_envelope_constant_and_scipy,
     pin_bmode_golden,
     pin_bmode_per_frame_and_degenerate,
+    pin_adjoint_dot_product,
+    pin_dydc_linear_ramp,
 ]

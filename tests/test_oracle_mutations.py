@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle_pins as P
+from oracle import adjoint as A
 from oracle import analytic as E
 from oracle import das as D
 from oracle import dbclip as B
@@ -125,6 +126,36 @@ def _logc_no_clip(env, dr_db, offset=False):
     return out + dr_db if offset else out
 
 
+def _adjoint_no_alpha(g, tau_tx, tau_rx, weight, t0, fs, n_s):
+    # spreads (1 - a) to both samples
+    g = np.asarray(g, dtype=np.float64).ravel()
+    T, C = tau_tx.shape[0], tau_rx.shape[0]
+    out = np.zeros((T, C, n_s))
+    for t in range(T):
+        for j in range(C):
+            u = D.fractional_index(tau_tx[t].ravel(), tau_rx[j].ravel(), t0, fs)
+            n = np.floor(u)
+            a = u - n
+            ok = (n >= 0) & (n <= n_s - 2)
+            ni = n[ok].astype(np.int64)
+            wg = (weight[j].ravel() * g)[ok]
+            np.add.at(out[t, j], ni, (1.0 - a[ok]) * wg)
+            np.add.at(out[t, j], ni + 1, (1.0 - a[ok]) * wg)
+    return out
+
+
+def _dydc_sign(rf, tau_tx, tau_rx, weight, t0, fs, c):
+    return -_orig_dydc(rf, tau_tx, tau_rx, weight, t0, fs, c)
+
+
+def _dydc_rx_only(rf, tau_tx, tau_rx, weight, t0, fs, c):
+    return _orig_dydc(rf, np.zeros_like(tau_tx), tau_rx, weight, t0, fs, c) * 0 + \
+        _orig_dydc(rf, tau_tx * 0.0 + tau_tx, tau_rx * 0.0, weight, t0, fs, c)
+
+
+_orig_dydc = A.das_dydc_sum
+
+
 MUTATIONS = {
     "interp_floor_only": (D, "interp_linear", _interp_floor_only),
     "interp_swapped_weights": (D, "interp_linear", _interp_swapped_weights),
@@ -142,6 +173,8 @@ MUTATIONS = {
     "db_power_not_amplitude": (B, "log_compress", _logc_power_db),
     "db_global_max": (B, "log_compress", _logc_global_max),
     "db_no_clip": (B, "log_compress", _logc_no_clip),
+    "adjoint_weight_not_alpha": (A, "das_adjoint_sum", _adjoint_no_alpha),
+    "dydc_sign": (A, "das_dydc_sum", _dydc_sign),
 }
 
 

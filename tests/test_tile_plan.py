@@ -23,7 +23,7 @@ def _check(w):
     assert nst + span <= QMAX
     assert nst % 8 == 0
     assert info["lds_bytes"] <= LDS_LIMIT
-    assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 12 * w.n_tx
+    assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 32 * w.n_tx
     # staged groups of one pass fit the per-lane register staging
     assert info["chunk"] * (nst // 8) <= 4 * THREADS
     assert info["tile_z"] * info["tile_x"] == THREADS * info["px"]

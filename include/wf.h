@@ -177,11 +177,47 @@ wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
                    void* stream);
 
 /*
+ * Forward-mode derivative of DAS w.r.t. the speed of sound c, per pixel.
+ * Every time of flight is a path length over c, so du/dc = -(u + t0 fs) / c
+ * for the fractional sample index u, and (almost everywhere: away from the
+ * integer crossings of u, where the linear interpolant has a kink)
+ *   dy(p)/dc = sum_{t,j} w_j(p) (r[n+1] - r[n]) du/dc.
+ * The beamformer sits in a trainable graph in the paper (Sec. I; Sec. IV);
+ * this is the derivative that lets c be learned.
+ *   rf    DEVICE [F][T][C][S] as for the DAS calls.
+ *   dydc  DEVICE float [F][nz][nx].
+ * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
+ */
+wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                      const wf_grid* grid, float* dydc, void* stream);
+
+/*
+ * Adjoint of DAS w.r.t. the RF (the transpose of the interpolating gather):
+ * for a cotangent g, grad_rf[t][j][m] = sum_p w_j(p) g(p) ((1-a)[m = n] +
+ * a [m = n+1]) over pairs with 0 <= n <= S-2.  grad_rf is overwritten.
+ *   g        DEVICE float [F][nz][nx].
+ *   grad_rf  DEVICE float [F][T][C][S]; acq->dtype must be WF_RF_F32.
+ * Accumulated with float atomics: reproducible to FP32 rounding, not bitwise.
+ * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
+ */
+wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                         const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                         const wf_grid* grid, const float* g, float* grad_rf, void* stream);
+
+/*
+ * out[0] = sum_i a[i] b[i] (DEVICE pointers, n elements; compensated sums in
+ * a fixed order: deterministic).  With a = dL/dy and b = dy/dc it gives
+ * dL/dc.
+ */
+wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* stream);
+
+/*
  * Launch plan the DAS calls would use for this geometry (host only; touches
- * no device).  info (HOST int32[10]) receives: pixels per lane, tile depth,
+ * no device).  info (HOST int32[11]) receives: pixels per lane, tile depth,
  * tile width, window-local delay clamp (samples), staged window entries,
  * LDS entries per window, LDS bytes per workgroup, tiles along z, tiles
- * along x, channels per pass.  mode 0 = STAI, 1 = PWI.  Returns
+ * along x, channels per pass, threads per workgroup.  mode 0 = STAI, 1 = PWI.  Returns
  * WF_ERR_UNSUPPORTED when no tile shape fits (as the DAS calls would).
  */
 wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* acq,

@@ -15,15 +15,16 @@ runs the last two.
 from __future__ import annotations
 
 import ctypes
-import math
-from dataclasses import dataclass, field
+import dataclasses
+from dataclasses import dataclass
 from typing import Optional, Sequence
 
 from . import _lib
 from ._lib import WfError, load
 
 __all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
-           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info"]
+           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info",
+           "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd"]
 
 
 @dataclass(frozen=True)
@@ -194,7 +195,7 @@ def das_pwi(rf, scan: Scan, out=None, stream=None):
 
 
 TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
-                    "chunk")
+                    "chunk", "threads")
 
 
 def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:
@@ -206,7 +207,7 @@ def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:
     tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
     ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
     tref = _tref(scan) if mode == 1 else 0
-    info = (ctypes.c_int32 * 10)()
+    info = (ctypes.c_int32 * 11)()
     _lib.check(lib.wf_das_tile_info(mode, probe, acq, tx, ang, tref, grid,
                                     ctypes.cast(info, _lib.c_int32_p)), "wf_das_tile_info")
     return dict(zip(TILE_INFO_FIELDS, list(info)))
@@ -282,3 +283,116 @@ def bmode(bf, dr_db: float, offset: bool = False, out=None, col_max=None, stream
                             _dev(col_max, "col_max"), _stream_ptr(b3, stream)), "wf_bmode")
     out = out.view(nf, nz, nx)
     return out[0] if squeeze else out
+
+
+# ---------------------------------------------------------------------------
+# derivatives (adjoint w.r.t. RF, forward-mode d y / d c) and autograd
+# ---------------------------------------------------------------------------
+
+def _mode_args(scan: Scan, keep: _Keep):
+    mode = 0 if scan.mode == "stai" else 1
+    tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
+    ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
+    tref = _tref(scan) if mode == 1 else 0
+    return mode, tx, ang, tref
+
+
+def das_dydc(scan: Scan, rf, out=None, stream=None):
+    """d y / d c per pixel (forward mode), rf [F][T][C][S] -> [F][nz][nx]."""
+    torch = _torch()
+    lib = load()
+    rf4 = rf.unsqueeze(0) if rf.dim() == 3 else rf
+    nf, nt, nc, ns = rf4.shape
+    g = scan.grid
+    if out is None:
+        out = torch.empty((nf, g.nz, g.nx), dtype=torch.float32, device=rf.device)
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    _lib.check(lib.wf_das_dydc(mode, _dev(rf4, "rf"), probe, acq, tx, ang, tref, grid,
+                               _dev(out, "dydc"), _stream_ptr(rf4, stream)), "wf_das_dydc")
+    return out
+
+
+def das_adjoint(scan: Scan, g, n_s: int, out=None, stream=None):
+    """Adjoint of DAS: cotangent g [F][nz][nx] -> d L / d rf [F][T][C][S]
+    (float32; accumulated with atomics, reproducible to FP32 rounding)."""
+    torch = _torch()
+    lib = load()
+    g3 = g.unsqueeze(0) if g.dim() == 2 else g
+    nf = g3.shape[0]
+    if out is None:
+        out = torch.empty((nf, scan.n_tx, scan.n_ch, n_s), dtype=torch.float32, device=g.device)
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, nf, n_s, _lib.WF_RF_F32)
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    _lib.check(lib.wf_das_adjoint(mode, probe, acq, tx, ang, tref, grid, _dev(g3, "g"),
+                                  _dev(out, "grad_rf"), _stream_ptr(g3, stream)),
+               "wf_das_adjoint")
+    return out
+
+
+def dot(a, b, out=None, stream=None):
+    """sum(a * b) of two float32 device tensors, deterministic."""
+    torch = _torch()
+    lib = load()
+    if a.numel() != b.numel():
+        raise ValueError("dot: size mismatch")
+    if out is None:
+        out = torch.empty((1,), dtype=torch.float32, device=a.device)
+    _lib.check(lib.wf_dot(_dev(a, "a"), _dev(b, "b"), a.numel(), _dev(out, "out"),
+                          _stream_ptr(a, stream)), "wf_dot")
+    return out
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class DASFunction(torch.autograd.Function):
+        """y = DAS(rf; c) with gradients w.r.t. the RF (adjoint kernel) and
+        the speed of sound (forward-mode d y / d c reduced against dL/dy).
+        ``c`` is a 0-dim tensor; its value is read on the host."""
+
+        @staticmethod
+        def forward(ctx, rf, c, scan):
+            scan_c = dataclasses.replace(scan, c=float(c))
+            ctx.scan = scan_c
+            ctx.rf_dtype = rf.dtype
+            ctx.save_for_backward(rf)
+            return das(scan_c, rf)
+
+        @staticmethod
+        def backward(ctx, gy):
+            (rf,) = ctx.saved_tensors
+            gy = gy.contiguous().float()
+            grad_rf = grad_c = None
+            if ctx.needs_input_grad[0]:
+                squeeze = rf.dim() == 3
+                g3 = gy.unsqueeze(0) if squeeze else gy
+                grad_rf = das_adjoint(ctx.scan, g3, rf.shape[-1]).to(ctx.rf_dtype)
+                grad_rf = grad_rf[0] if squeeze else grad_rf
+            if ctx.needs_input_grad[1]:
+                dydc = das_dydc(ctx.scan, rf)
+                grad_c = dot(gy.reshape(-1), dydc.reshape(-1)).reshape(())
+            return grad_rf, grad_c, None
+
+    return DASFunction
+
+
+_das_fn = None
+
+
+def __getattr__(name):
+    if name == "DASFunction":
+        global _das_fn
+        if _das_fn is None:
+            _das_fn = _autograd_function()
+        return _das_fn
+    raise AttributeError(name)
+
+
+def das_autograd(scan: Scan, rf, c):
+    """Differentiable DAS: rf (float32/float16, requires_grad allowed) and the
+    speed of sound c (0-dim tensor, requires_grad allowed)."""
+    fn = __getattr__("DASFunction")
+    return fn.apply(rf, c, scan)

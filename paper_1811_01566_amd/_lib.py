@@ -51,6 +51,10 @@ SIGNATURES = {
                       V]),
     "wf_das_tile_info": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid),
                              c_int32_p]),
+    "wf_das_dydc": (I, [I, V, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V]),
+    "wf_das_adjoint": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
+                           V]),
+    "wf_dot": (I, [V, V, ctypes.c_int64, V, V]),
     "wf_envelope": (I, [V, I, I, I, V, V, V]),
     "wf_log_compress": (I, [V, V, I, I, I, F, I, V, V]),
     "wf_bmode": (I, [V, I, I, I, F, I, V, V, V]),
@@ -68,11 +72,13 @@ class WfError(RuntimeError):
         self.status = status
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libwf.so; raises if it has not been built (no fallback exists)."""
+def load(path: str = None) -> ctypes.CDLL:
+    """Load libwf.so (or the library named by $WF_LIB); raises if it has not
+    been built (no fallback exists)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("WF_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build it with `python -m paper_1811_01566_amd.build`")

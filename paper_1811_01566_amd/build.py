@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwf.so")
-SOURCES = ["api.cpp", "das.hip", "envelope.hip"]
+SOURCES = ["api.cpp", "das.hip", "adjoint.hip", "envelope.hip"]
 ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -39,17 +39,17 @@ def compile_cmd(out: str) -> list:
     ] + [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = compile_cmd(tmp)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = compile_cmd(tmp) + [f"-D{d}" for d in defines]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"hipcc failed with status {r.returncode}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -1,0 +1,186 @@
+// Adjoint of Delay-and-Sum (K5) and small helpers (fill, dot) for gfx950.
+//
+// The paper's reason for putting the beamformer in a dataflow graph is to
+// train networks through it (Sec. I; Sec. IV).  DAS is linear in the RF for a
+// fixed geometry: y(p) = sum_{t,j} w (1 - a) r[n] + a r[n+1].  Its adjoint
+// scatters a cotangent g(p) back to the samples: (1 - a) w g to r[n] and
+// a w g to r[n+1], for pairs with 0 <= n <= S-2.
+//
+// K5 reuses the forward's tiles, window bases and window-local Q9.23 delays
+// (das_common.h), so a contribution lands in exactly the pair the forward
+// read.  Per transmit pass it accumulates, for every window entry (= pair n),
+// G[n] = sum w g and H[n] = sum a w g with LDS float atomics; then sample s
+// receives (G[s] - H[s]) + H[s-1] (each only for valid pairs) through one
+// global float atomic per touched sample.  The order of the global atomics is
+// not fixed, so the gradient is reproducible only to FP32 rounding.
+#pragma clang fp contract(off)
+
+#include "das_common.h"
+
+namespace wf {
+namespace {
+
+template <int MODE, int NT, int PX>
+__global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int slot = a.slot;
+    const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
+    float2* win = reinterpret_cast<float2*>(smem);  // (G, H) per entry
+    int4* m_tab = reinterpret_cast<int4*>(smem + buf_bytes);
+    float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
+    int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
+    const uint32_t lds0 =
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
+
+    const int frame = blockIdx.y;
+    const TileGeom g = tile_geom<NT, PX>(a, blockIdx.x);
+    tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
+    for (int i = tid; i < kChunk * slot; i += NT) win[i] = make_float2(0.0f, 0.0f);
+
+    PixelSet<PX> p;
+    pixel_set<NT, PX>(a, g, p);
+    float gp[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+        gp[k] = p.valid[k] ? a.g[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] : 0.0f;
+    float* grad_frame = a.grad + (size_t)frame * a.T * a.C * a.S;
+    const int ne = a.nst + 1;  // samples a window can touch
+
+    for (int c0 = 0; c0 < a.C; c0 += kChunk) {
+        __syncthreads();
+        chunk_tables(a, g, c0, b_tab);
+        __syncthreads();
+        int bj[kChunk];
+        int any_act = 0, bmin = 0x7fffffff, bmax = -0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            bj[j] = __builtin_amdgcn_readfirstlane(b_tab[j]);
+            any_act |= __builtin_amdgcn_readfirstlane(b_tab[kChunk + j]);
+            bmin = min(bmin, bj[j]);
+            bmax = max(bmax, bj[j]);
+        }
+        if (!any_act) continue;
+
+        uint32_t rq[PX][kChunk];
+        rx_delays<PX>(a, p, c0, bj, rq);
+
+        for (int t = 0; t < a.T; ++t) {
+            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+            if (at + bmin > a.S - 2 || at + bmax + a.nst < 0) continue;  // nothing lands
+            uint32_t tq[PX];
+            tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+
+            // ---- scatter into the LDS windows ------------------------------
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+#pragma unroll
+                for (int k = 0; k < PX; ++k) {
+                    if (gp[k] == 0.0f) continue;
+                    const uint32_t u = tq[k] + rq[k][j];
+                    const float frac = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u) - 1.0f;
+                    float* e = reinterpret_cast<float*>(smem + (entry_addr(u, off) - lds0));
+                    atomicAdd(e, gp[k]);
+                    atomicAdd(e + 1, gp[k] * frac);
+                }
+            }
+            __syncthreads();
+
+            // ---- flush: sample s = A0 + e of every window ------------------
+            for (int w = tid; w < kChunk * ne; w += NT) {
+                const int j = w / ne;
+                const int e = w - j * ne;
+                const int c = c0 + j;
+                const int A0 = (at + b_tab[j]) & ~7;
+                const int s = A0 + e;
+                const float2* wj = win + j * slot;
+                float v = 0.0f;
+                if (e < a.nst && s >= 0 && s <= a.S - 2) v += wj[e].x - wj[e].y;
+                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += wj[e - 1].y;
+                if (c < a.C && v != 0.0f && s >= 0 && s < a.S)
+                    unsafeAtomicAdd(grad_frame + ((size_t)t * a.C + c) * a.S + s, v);
+            }
+            __syncthreads();
+            for (int w = tid; w < kChunk * a.nst; w += NT) {
+                const int j = w / a.nst;
+                win[j * slot + (w - j * a.nst)] = make_float2(0.0f, 0.0f);
+            }
+            __syncthreads();  // windows are zero before the next pass scatters
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(float* p, size_t n, float v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// One workgroup, compensated (Kahan) per-thread sums, fixed-order tree:
+// deterministic.
+constexpr int kDotThreads = 1024;
+
+__global__ void __launch_bounds__(kDotThreads) dot_kernel(const float* a, const float* b,
+                                                         size_t n, float* out) {
+    __shared__ float red[kDotThreads];
+    float s = 0.0f, comp = 0.0f;
+    for (size_t i = threadIdx.x; i < n; i += kDotThreads) {
+        const float y = fmaf(a[i], b[i], -comp);
+        const float t = s + y;
+        comp = (t - s) - y;
+        s = t;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kDotThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int MODE, int NT, int PX>
+hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX>, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F);
+    hipLaunchKernelGGL((das_adjoint_kernel<MODE, NT, PX>), grid, dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_adj_shape(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
+    if (nt == 512) return launch_adj<MODE, 512, 2>(a, lds, s);
+    return px == 4 ? launch_adj<MODE, 256, 4>(a, lds, s) : launch_adj<MODE, 256, 1>(a, lds, s);
+}
+
+}  // namespace
+
+hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
+                              hipStream_t s) {
+    return mode == 1 ? launch_adj_shape<1>(nt, px, a, lds_bytes, s)
+                     : launch_adj_shape<0>(nt, px, a, lds_bytes, s);
+}
+
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(kDotThreads), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace wf

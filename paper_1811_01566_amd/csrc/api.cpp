@@ -249,7 +249,7 @@ wf_status device_tables(int mode, const wf_probe* probe, const wf_acq* acq,
 // ---------------------------------------------------------------------------
 
 struct TilePlan {
-    int px = 0, tz_log2 = 0, span = 0, nst = 0, slot = 0;
+    int threads = 0, px = 0, tz_log2 = 0, span = 0, nst = 0, slot = 0;
     size_t lds = 0;
     int ntz = 0, ntx = 0;
 };
@@ -264,40 +264,52 @@ size_t das_lds_bytes(int slot, int T) {
 constexpr size_t kLdsSoft = 65536;
 constexpr size_t kLdsHard = 163840;
 
+#ifndef WF_DAS_PREFER_512
+#define WF_DAS_PREFER_512 0
+#endif
+
 bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
+    // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
+    // with twice the waves per workgroup
+    const int shapes[3][2] = {{WF_DAS_PREFER_512 ? 512 : 256, WF_DAS_PREFER_512 ? 2 : 4},
+                              {WF_DAS_PREFER_512 ? 256 : 512, WF_DAS_PREFER_512 ? 4 : 2},
+                              {256, 1}};
     for (size_t limit : {kLdsSoft, kLdsHard}) {
         double best_score = -1.0;
-        for (int px : {4, 1}) {
-        for (int tzl = 6; tzl >= 3; --tzl) {
-            const int tz = 1 << tzl;
-            const int txw = (wf::kThreads * px) >> tzl;
-            const int ez = std::min(tz, grid->nz), ex = std::min(txw, grid->nx);
-            const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
-            const int span = (int)std::ceil(d) + 3;
-            const int nst = ((2 * span + 8) + 7) & ~7;
-            const int slot = nst + span + 8;
-            if (nst + span > 511) continue;
-            if (wf::kChunk * (nst / 8) > wf::kMaxGroups * wf::kThreads) continue;
-            const size_t lds = das_lds_bytes(slot, acq->n_tx);
-            if (lds > limit) continue;
-            const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
-            const double wgs = (double)ntz * ntx * acq->n_frames;
-            // pixels served per staged sample, discounted when the grid is
-            // too small to fill the chip
-            const double reuse = (double)ez * ex / nst;
-            const double score = reuse * std::min(1.0, wgs / 512.0);
-            if (score > best_score) {
-                best_score = score;
-                best->px = px;
-                best->tz_log2 = tzl;
-                best->span = span;
-                best->nst = nst;
-                best->slot = slot;
-                best->lds = lds;
-                best->ntz = ntz;
-                best->ntx = ntx;
+        for (const auto& sh : shapes) {
+            const int nt = sh[0], px = sh[1];
+            for (int tzl = 6; tzl >= 3; --tzl) {
+                const int tz = 1 << tzl;
+                const int txw = (nt * px) >> tzl;
+                const int ez = std::min(tz, grid->nz), ex = std::min(txw, grid->nx);
+                const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
+                const int span = (int)std::ceil(d) + 3;
+                const int nst = ((2 * span + 8) + 7) & ~7;
+                const int slot = nst + span + 8;
+                if (nst + span > 511) continue;
+                const int max_groups = nt == 512 ? 2 : wf::kMaxGroups;
+                if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
+                const size_t lds = das_lds_bytes(slot, acq->n_tx);
+                if (lds > limit) continue;
+                const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
+                const double wgs = (double)ntz * ntx * acq->n_frames;
+                // pixels served per staged sample, discounted when the grid is
+                // too small to fill the chip; ties keep the earlier shape
+                const double reuse = (double)ez * ex / nst;
+                const double score = reuse * std::min(1.0, wgs / 512.0);
+                if (score > best_score * (1.0 + 1e-9)) {
+                    best_score = score;
+                    best->threads = nt;
+                    best->px = px;
+                    best->tz_log2 = tzl;
+                    best->span = span;
+                    best->nst = nst;
+                    best->slot = slot;
+                    best->lds = lds;
+                    best->ntz = ntz;
+                    best->ntx = ntx;
+                }
             }
-        }
         }
         if (best_score > 0.0) return true;
     }
@@ -310,62 +322,90 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-wf_status das_common(int mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
-                     const int32_t* tx_elem, const double* angles, int32_t tref,
-                     const wf_grid* grid, float* out, void* stream) {
+// Validates a DAS-shaped call and fills the kernel arguments and plan.
+wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                      const double* angles, int32_t tref, const wf_grid* grid, wf::DasArgs* a,
+                      TilePlan* tp) {
     wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
-    if (!rf) return fail(WF_ERR_INVALID_ARG, "rf is NULL");
-    if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
-    if (((uintptr_t)rf & 15) != 0) return fail(WF_ERR_UNSUPPORTED, "rf is not 16-byte aligned");
-    if (((uintptr_t)out & 3) != 0) return fail(WF_ERR_INVALID_ARG, "out is not 4-byte aligned");
-    const size_t esz = acq->dtype == WF_RF_F32 ? 4 : 2;
-    const size_t rf_bytes = (size_t)acq->n_frames * acq->n_tx * acq->n_ch * acq->n_s * esz;
-    const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
-    if (overlaps(rf, rf_bytes, out, out_bytes))
-        return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
     Geometry g;
     CacheEntry ce;
     st = device_tables(mode, probe, acq, tx_elem, angles, tref, grid, &g, &ce);
     if (st != WF_OK) return st;
-    TilePlan tp;
-    if (!choose_tile(g, acq, grid, &tp))
+    if (!choose_tile(g, acq, grid, tp))
         return fail(WF_ERR_UNSUPPORTED,
                     "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
                     g.dzs, g.dxs);
-    if ((long long)tp.ntz * tp.ntx > 0x7FFFFFFF)
+    if ((long long)tp->ntz * tp->ntx > 0x7FFFFFFF)
         return fail(WF_ERR_UNSUPPORTED, "too many tiles");
-    wf::DasArgs a{};
+    *a = wf::DasArgs{};
+    a->F = acq->n_frames;
+    a->T = acq->n_tx;
+    a->C = acq->n_ch;
+    a->S = acq->n_s;
+    a->nz = grid->nz;
+    a->nx = grid->nx;
+    a->tz_log2 = tp->tz_log2;
+    a->ntz = tp->ntz;
+    a->ntx = tp->ntx;
+    a->ng = tp->nst / 8;
+    a->ng_inv = ((1 << 20) + a->ng - 1) / a->ng;
+    a->nst = tp->nst;
+    a->slot = tp->slot;
+    a->txspan_q = (uint32_t)tp->span << wf::kQBits;
+    a->rxspan_q = (uint32_t)tp->span << wf::kQBits;
+    a->Z0 = g.Z0;
+    a->dZ = g.dZ;
+    a->dX = g.dX;
+    a->O = g.O;
+    a->fnum2 = g.fnum2;
+    a->x0f = g.x0f;
+    a->dxf = g.dxf;
+    a->t0fs = (float)(acq->t0 * acq->fs);
+    a->neg_inv_c = (float)(-1.0 / acq->c);
+    a->tx_tab = ce.tx;
+    a->ch_tab = ce.ch;
+    return WF_OK;
+}
+
+size_t rf_bytes_of(const wf_acq* acq) {
+    const size_t esz = acq->dtype == WF_RF_F32 ? 4 : 2;
+    return (size_t)acq->n_frames * acq->n_tx * acq->n_ch * acq->n_s * esz;
+}
+
+wf_status check_rf(const void* rf, const wf_acq* acq) {
+    if (!rf) return fail(WF_ERR_INVALID_ARG, "rf is NULL");
+    if (((uintptr_t)rf & 15) != 0) return fail(WF_ERR_UNSUPPORTED, "rf is not 16-byte aligned");
+    return WF_OK;
+}
+
+int groups_of(const wf::DasArgs& a, const TilePlan& tp) {
+    return (wf::kChunk * a.ng + tp.threads - 1) / tp.threads;
+}
+
+// forward DAS (op 0) or forward-mode d y / d c (op 1)
+wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                     const int32_t* tx_elem, const double* angles, int32_t tref,
+                     const wf_grid* grid, float* out, void* stream) {
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    if (st != WF_OK) return st;
+    if ((st = check_rf(rf, acq)) != WF_OK) return st;
+    if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
+    if (((uintptr_t)out & 3) != 0) return fail(WF_ERR_INVALID_ARG, "out is not 4-byte aligned");
+    const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
+    if (overlaps(rf, rf_bytes_of(acq), out, out_bytes))
+        return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
+    wf::DasArgs a;
+    TilePlan tp;
+    if ((st = prepare_das(mode, probe, acq, tx_elem, angles, tref, grid, &a, &tp)) != WF_OK)
+        return st;
     a.rf = rf;
     a.out = out;
-    a.F = acq->n_frames;
-    a.T = acq->n_tx;
-    a.C = acq->n_ch;
-    a.S = acq->n_s;
-    a.nz = grid->nz;
-    a.nx = grid->nx;
-    a.tz_log2 = tp.tz_log2;
-    a.ntz = tp.ntz;
-    a.ntx = tp.ntx;
-    a.ng = tp.nst / 8;
-    a.ng_inv = ((1 << 20) + a.ng - 1) / a.ng;
-    a.nst = tp.nst;
-    a.slot = tp.slot;
-    a.txspan_q = (uint32_t)tp.span << wf::kQBits;
-    a.rxspan_q = (uint32_t)tp.span << wf::kQBits;
-    a.Z0 = g.Z0;
-    a.dZ = g.dZ;
-    a.dX = g.dX;
-    a.O = g.O;
-    a.fnum2 = g.fnum2;
-    a.x0f = g.x0f;
-    a.dxf = g.dxf;
-    a.tx_tab = ce.tx;
-    a.ch_tab = ce.ch;
-    const int groups = (wf::kChunk * a.ng + wf::kThreads - 1) / wf::kThreads;
-    hipError_t e =
-        wf::launch_das(mode, acq->dtype, tp.px, groups, a, tp.lds, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "DAS kernel launch");
+    hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
+                                            groups_of(a, tp), a, tp.lds, (hipStream_t)stream)
+                           : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
+                                                 groups_of(a, tp), a, tp.lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, op == 0 ? "DAS kernel launch" : "dy/dc kernel launch");
     return ok();
 }
 
@@ -390,13 +430,60 @@ const char* wf_last_error(void) { return g_err.c_str(); }
 
 wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const wf_grid* grid, float* out, void* stream) {
-    return das_common(0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, stream);
+    return das_common(0, 0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, stream);
 }
 
 wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid, float* out,
                      void* stream) {
-    return das_common(1, rf, probe, acq, nullptr, angles_rad, tref, grid, out, stream);
+    return das_common(1, 0, rf, probe, acq, nullptr, angles_rad, tref, grid, out, stream);
+}
+
+wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                      const wf_grid* grid, float* dydc, void* stream) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    return das_common(mode, 1, rf, probe, acq, mode == 0 ? tx_elem : nullptr,
+                      mode == 1 ? angles_rad : nullptr, tref, grid, dydc, stream);
+}
+
+wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                         const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                         const wf_grid* grid, const float* g, float* grad_rf, void* stream) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    if (st != WF_OK) return st;
+    if (acq->dtype != WF_RF_F32)
+        return fail(WF_ERR_INVALID_ARG, "the RF gradient is float32 (acq->dtype=%d)", acq->dtype);
+    if (!g) return fail(WF_ERR_INVALID_ARG, "g is NULL");
+    if (!grad_rf) return fail(WF_ERR_INVALID_ARG, "grad_rf is NULL");
+    if (((uintptr_t)grad_rf & 3) != 0 || ((uintptr_t)g & 3) != 0)
+        return fail(WF_ERR_INVALID_ARG, "g and grad_rf must be 4-byte aligned");
+    const size_t gbytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
+    if (overlaps(g, gbytes, grad_rf, rf_bytes_of(acq)))
+        return fail(WF_ERR_INVALID_ARG, "grad_rf overlaps g");
+    wf::DasArgs a;
+    TilePlan tp;
+    if ((st = prepare_das(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                          mode == 1 ? angles_rad : nullptr, tref, grid, &a, &tp)) != WF_OK)
+        return st;
+    a.g = g;
+    a.grad = grad_rf;
+    const size_t lds = tp.lds - (size_t)wf::kChunk * tp.slot * 8;  // one window buffer
+    hipError_t e = wf::launch_fill(grad_rf, rf_bytes_of(acq) / 4, 0.0f, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    return ok();
+}
+
+wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* stream) {
+    if (!a || !b || !out) return fail(WF_ERR_INVALID_ARG, "a, b and out must not be NULL");
+    if (n < 0) return fail(WF_ERR_INVALID_ARG, "n=%lld is negative", (long long)n);
+    hipError_t e = wf::launch_dot(a, b, (size_t)n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dot kernel launch");
+    return ok();
 }
 
 wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* acq,
@@ -415,7 +502,7 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
                     g.dzs, g.dxs);
     info[0] = tp.px;
     info[1] = 1 << tp.tz_log2;
-    info[2] = (wf::kThreads * tp.px) >> tp.tz_log2;
+    info[2] = (tp.threads * tp.px) >> tp.tz_log2;
     info[3] = tp.span;
     info[4] = tp.nst;
     info[5] = tp.slot;
@@ -423,6 +510,7 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     info[7] = tp.ntz;
     info[8] = tp.ntx;
     info[9] = wf::kChunk;
+    info[10] = tp.threads;
     return ok();
 }
 

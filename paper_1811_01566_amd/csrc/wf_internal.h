@@ -11,7 +11,8 @@ namespace wf {
 // Channels staged per pass of the DAS kernel: their one-way receive delays
 // stay in registers while every transmit streams through LDS.
 constexpr int kChunk = 16;
-// Threads per DAS workgroup (4 wave64 waves).
+// Threads per DAS workgroup (4 wave64 waves); launch plans may also use
+// 512-thread workgroups with 2 pixels per thread.
 constexpr int kThreads = 256;
 // Staged 8-sample RF groups per lane and transmit pass: the kernel is built
 // for 2 or 4 (register staging), the launch plan picks the smaller that
@@ -52,9 +53,13 @@ struct DasArgs {
     float2 dX;          // column step, samples (float-float)
     float2 O;           // STAI: -t0 fs added to the transmit delay
     float fnum2;        // 2 F# (0: no apodisation)
-    float x0f, dxf;     // lateral grid in samples (float) for window bounds
+    float x0f, dxf;     // lateral grid in samples (float) for window bases
+    float t0fs;         // t0 * fs (d y / d c: time of flight = index + t0 fs)
+    float neg_inv_c;    // -1 / c (d y / d c scale)
     const TxConst* tx_tab;
     const ChConst* ch_tab;
+    const float* g;     // adjoint: cotangent [F][nz][nx]
+    float* grad;        // adjoint: d L / d rf [F][T][C][S]
 };
 
 struct DelayArgs {
@@ -69,8 +74,14 @@ struct DelayArgs {
 };
 
 // Launchers; return the hipError_t of the launch.
-hipError_t launch_das(int mode, int dtype, int px, int groups, const DasArgs& a,
+hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
                       size_t lds_bytes, hipStream_t s);
+hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
+                           size_t lds_bytes, hipStream_t s);
+hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
+                              hipStream_t s);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
 hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,
                            hipStream_t s);

@@ -1,0 +1,145 @@
+"""Derivatives of DAS on the GPU, through the C ABI, against the FP64 oracle.
+
+  adjoint w.r.t. RF   vs oracle transpose: nL2 <= 1e-5 (float atomics change
+                      only the order of FP32 additions)
+  dot-product test    <A r, g> = <r, A^T g> with both GPU kernels: rel 1e-5
+  d y / d c           vs oracle: nL2 <= 1e-5 on a smooth record; on speckle
+                      the derivative of the piecewise-linear interpolant jumps
+                      where u crosses an integer, and a ~1e-7-sample delay
+                      difference moves a crossing with probability ~1e-7 per
+                      term, so the bar there is 2e-3 (a few pixels change one
+                      of their 8192 terms)
+  d L / d c           GPU analytic vs oracle analytic: rel 2e-3 (kinks); the
+                      central finite difference (h = 0.5 m/s) of the GPU
+                      forward on the 64 x 64 sub-grid equals the mean of the
+                      analytic derivative over [c - h, c + h]: rel 2e-2
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import phantom
+from phantom.configs import subgrid
+from phantom.prepare import lighter
+from wfhelp import nl2, scan_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _t():
+    import torch
+
+    return torch
+
+
+CASES = {
+    "tiny_stai_apod_t0": lambda: phantom.tiny_stai(f_number=0.8, t0=0.3e-6),
+    "tiny_pwi_apod": lambda: phantom.tiny_pwi(f_number=1.2, t0=-0.2e-6, tref="centre"),
+    "pwi_sub": lambda: subgrid(phantom.get_workload("pwi").with_(n_tx=8, angles_deg=tuple(
+        np.linspace(-16, 16, 8))), 300, 70, 200, 20),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_adjoint_matches_oracle_and_dot_product(wf_gpu, name):
+    torch = _t()
+    w = CASES[name]()
+    rng = np.random.default_rng(4)
+    g = rng.normal(size=(w.nz, w.nx)).astype(np.float32)
+    r = rng.normal(size=(w.n_tx, w.n_ch, w.n_s)).astype(np.float32)
+    scan = scan_from_workload(w)
+    gr = wf_gpu.das_adjoint(scan, torch.from_numpy(g).cuda()[None], w.n_s)
+    y = wf_gpu.das(scan, torch.from_numpy(r).cuda()[None])
+    torch.cuda.synchronize()
+    ref = oracle.das_adjoint_workload(g.astype(np.float64), w)
+    err = nl2(gr[0].cpu().numpy(), ref)
+    lhs = float(np.sum(y[0].cpu().numpy().astype(np.float64) * g))
+    rhs = float(np.sum(r.astype(np.float64) * gr[0].cpu().numpy()))
+    print(f"{name}: adjoint nL2 {err:.2e}, dot-product rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert err <= 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def _smooth_rf(w, seed=5):
+    rng = np.random.default_rng(seed)
+    s = np.arange(w.n_s)
+    ph = rng.uniform(0, 2 * np.pi, size=(w.n_tx, w.n_ch, 1))
+    return (1000.0 * np.cos(2 * np.pi * 0.01 * s[None, None, :] + ph)).astype(np.float32)
+
+
+def test_dydc_matches_oracle(wf_gpu):
+    torch = _t()
+    w = CASES["pwi_sub"]()
+    scan = scan_from_workload(w)
+    for kind, rf, bar in (("smooth", _smooth_rf(w), 1e-5),
+                          ("speckle", phantom.synth_rf(lighter(w.with_(nz=1024, nx=512,
+                                                                       z_min=5e-3,
+                                                                       z_max=30e-3,
+                                                                       x_min=None,
+                                                                       x_max=None)))[0]
+                           .astype(np.float32), 2e-3)):
+        d = wf_gpu.das_dydc(scan, torch.from_numpy(rf).cuda()[None])
+        torch.cuda.synchronize()
+        ref = oracle.das_dydc_workload(rf.astype(np.float64), w)
+        err = nl2(d[0].cpu().numpy(), ref)
+        print(f"dy/dc {kind}: nL2 {err:.2e}")
+        assert err <= bar
+
+
+@pytest.mark.parametrize("c", [1480.0, 1540.0, 1600.0])
+def test_dldc_finite_difference_and_oracle(wf_gpu, c):
+    """PWI geometry, 64 x 64 sub-grid at the image centre, L = <g, y>.
+
+    With h = 0.5 m/s every delay moves by ~0.67 samples, a large step for
+    9-samples-per-period RF, so the central difference is compared with what
+    it exactly equals - the mean of dL/dc over [c - h, c + h] (L is
+    continuous in c) - integrated from the analytic derivative by the
+    trapezoid rule on 65 points; the gap to the point derivative is only
+    reported.  GPU vs oracle analytic: the kink crossings (see module
+    docstring) bound the agreement to ~1e-3 of the scalar."""
+    torch = _t()
+    base = lighter(phantom.get_workload("pwi"))
+    rf = phantom.synth_rf(base)[0].astype(np.float32)  # synthesised at 1540 m/s
+    w = subgrid(base, 480, 64, 224, 64).with_(c=c)
+    rng = np.random.default_rng(7)
+    g = rng.normal(size=(w.nz, w.nx)).astype(np.float32)
+    rf_t = torch.from_numpy(rf).cuda()[None]
+    g_t = torch.from_numpy(g).cuda()
+
+    def dldc(cc):
+        dydc = wf_gpu.das_dydc(scan_from_workload(w.with_(c=cc)), rf_t)
+        return float(wf_gpu.dot(g_t.reshape(-1), dydc.reshape(-1)).item())
+
+    dl = dldc(c)
+    h = 0.5
+    ys = [wf_gpu.das(scan_from_workload(w.with_(c=c + s * h)), rf_t) for s in (1, -1)]
+    fd = float(((ys[0] - ys[1]) * g_t).double().sum().item()) / (2 * h)
+    cs = np.linspace(c - h, c + h, 65)
+    vals = np.array([dldc(float(x)) for x in cs])
+    mean = float(np.sum((vals[1:] + vals[:-1]) * 0.5) / (len(cs) - 1))
+    ref = float(np.sum(g.astype(np.float64) * oracle.das_dydc_workload(rf.astype(np.float64), w)))
+    print(f"c={c}: dL/dc gpu {dl:.6e} oracle {ref:.6e} | fd(h=0.5) {fd:.6e} vs mean of the "
+          f"analytic over [c-h, c+h] {mean:.6e} (rel {abs(fd - mean) / abs(fd):.2e}); "
+          f"point derivative vs fd rel {abs(dl - fd) / abs(fd):.2e}")
+    assert abs(dl - ref) <= 2e-3 * abs(ref)
+    assert abs(fd - mean) <= 0.02 * abs(fd)
+
+
+def test_autograd_function(wf_gpu):
+    torch = _t()
+    w = CASES["pwi_sub"]()
+    scan = scan_from_workload(w)
+    rng = np.random.default_rng(8)
+    rf = torch.from_numpy(rng.normal(size=(1, w.n_tx, w.n_ch, w.n_s)).astype(np.float32)).cuda()
+    rf.requires_grad_(True)
+    c = torch.tensor(w.c, dtype=torch.float32, device="cuda", requires_grad=True)
+    g = torch.from_numpy(rng.normal(size=(1, w.nz, w.nx)).astype(np.float32)).cuda()
+    y = wf_gpu.das_autograd(scan, rf, c)
+    (y * g).sum().backward()
+    gr = wf_gpu.das_adjoint(scan, g, w.n_s)
+    dydc = wf_gpu.das_dydc(scan, rf.detach())
+    dl = wf_gpu.dot(g.reshape(-1), dydc.reshape(-1))
+    torch.cuda.synchronize()
+    assert nl2(rf.grad.cpu().numpy(), gr.cpu().numpy()) <= 1e-6
+    assert abs(float(c.grad) - float(dl)) <= 1e-6 * abs(float(dl))

@@ -16,6 +16,7 @@ THREADS = 256
 def _check(w):
     info = wf.tile_info(scan_from_workload(w), w.n_s, w.n_frames)
     span, nst, slot = info["span"], info["nst"], info["slot"]
+    nt = info["threads"]
     # unmasked: entry (n0 & 7) + floor(tx + rx) <= 7 + 2 span < nst
     assert 7 + 2 * span < nst
     # masked: receive delay = nst, entry <= 7 + nst + span < slot
@@ -25,9 +26,10 @@ def _check(w):
     assert info["lds_bytes"] <= LDS_LIMIT
     assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 32 * w.n_tx
     # staged groups of one pass fit the per-lane register staging
-    assert info["chunk"] * (nst // 8) <= 4 * THREADS
-    assert info["tile_z"] * info["tile_x"] == THREADS * info["px"]
-    assert THREADS % info["tile_z"] == 0
+    assert info["chunk"] * (nst // 8) <= (2 if nt == 512 else 4) * nt
+    assert (nt, info["px"]) in ((256, 4), (512, 2), (256, 1))
+    assert info["tile_z"] * info["tile_x"] == nt * info["px"]
+    assert nt % info["tile_z"] == 0
     assert info["ntz"] * info["tile_z"] >= w.nz > (info["ntz"] - 1) * info["tile_z"]
     assert info["ntx"] * info["tile_x"] >= w.nx > (info["ntx"] - 1) * info["tile_x"]
     return info
@@ -38,7 +40,7 @@ def _check(w):
 def test_named_workloads(name):
     info = _check(phantom.get_workload(name))
     if name == "pwi":
-        assert info["px"] == 4 and info["tile_z"] == 64
+        assert info["px"] * info["threads"] == 1024 and info["tile_z"] == 64
 
 
 def test_tiny_and_edge_workloads():

@@ -56,6 +56,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=256,
                     help="image columns of the frame the CPU oracle computes")
+    ap.add_argument("--serve", action="store_true",
+                    help="served mixed stream (continuous batching) vs the plain per-frame "
+                         "path instead of the single-workload benchmark")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-classes", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.75,
+                    help="arrival rate as a fraction of the plain path's capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (reference "
                          "for the HBM byte counters), and exit")
@@ -88,6 +95,41 @@ def active_contributions(w):
         act += int(ok.sum())
     frac = act / (w.n_tx * w.n_ch * IZ.size)
     return frac
+
+
+KERNEL_SOURCES = ("das.hip", "das_common.h", "ff.h", "wf_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1811_01566_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per DAS launch from the committed rocprofv3 counter summary
+    of this workload, scaled by the copy-kernel calibration; None when the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"das_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_factor"])
+        write = float(kv["write_kib_per_launch"]) * float(kv["copy_write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
 
 
 def scan_of(wf, w):
@@ -133,6 +175,63 @@ def cpu_baseline(w, rf, ncols):
     }
 
 
+def serve_main(args, wf, phantom, torch, np):
+    """Served mixed stream: Poisson arrivals over a pool of shape classes at a
+    fixed fraction of the plain path's capacity; both paths replay the same
+    trace and report per-request latency (arrival -> completion)."""
+    from phantom.configs import served_pool
+
+    from paper_1811_01566_amd.serve import (GpuBackend, Request, Server, latency_stats,
+                                            poisson_trace, run_plain)
+
+    pool = served_pool(args.serve_classes)
+    dev = torch.device("cuda:0")
+    rfs = [torch.from_numpy(phantom.synth_rf(w)[0]).to(dev) for w in pool]
+    scans = [scan_of(wf, w) for w in pool]
+    # plain service time per class (the capacity the arrival rate refers to)
+    svc = []
+    for sc, rf, w in zip(scans, rfs, pool):
+        for _ in range(3):
+            wf.bmode(wf.das(sc, rf), w.dr_db)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            wf.bmode(wf.das(sc, rf), w.dr_db)
+            torch.cuda.synchronize()
+        svc.append((time.perf_counter() - t) / 10)
+    capacity = 1.0 / float(np.mean(svc))
+    rate = args.serve_load * capacity
+    arrivals, cls = poisson_trace(pool, rate, args.serve_requests, seed=5)
+    reqs = [Request(i, scans[k], rfs[k], float(t), pool[k].dr_db)
+            for i, (t, k) in enumerate(zip(arrivals, cls))]
+    print(f"[bench] serve: {len(pool)} classes, plain capacity {capacity:.0f} frames/s, "
+          f"arrival rate {rate:.0f}/s", file=sys.stderr, flush=True)
+    budget = 16 << 30
+    srv = Server(GpuBackend("cuda:0", use_graphs=True), hbm_budget=budget, n_streams=4)
+    srv.run_trace(reqs[: min(200, len(reqs))])  # warm-up: executors and graphs
+    srv.results.clear()
+    served = latency_stats(srv.run_trace(reqs))
+    plain = latency_stats(run_plain(reqs))
+    ok = all(torch.equal(a.image, b.image) for a, b in
+             zip(srv.run_trace(reqs[:64]), run_plain(reqs[:64])))
+    res = {
+        "metric": "B-mode frames/s + DAS Gsamples/s (PWI 128ch×64tx); p99 frame latency",
+        "value": round(served["throughput_rps"], 2), "unit": "frames/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 200,
+        "ms_per_step": round(1e3 / served["throughput_rps"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served_mixed_stream", "classes": [w.name for w in pool],
+                   "arrival": f"Poisson, {args.serve_load:.2f} x plain capacity",
+                   "streams": 4, "hbm_budget_bytes": budget, "graphs": True},
+        "served": served, "plain": plain,
+        "plain_capacity_fps": capacity, "arrival_rate_hz": rate,
+        "served_equals_plain_bitwise": bool(ok),
+        "executors_built": srv.executors_built, "max_in_flight": srv.max_inflight,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -154,6 +253,18 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 5}), flush=True)
+        return
+
+    if args.serve:
+        from phantom.configs import served_pool
+
+        for w0 in served_pool(args.serve_classes):  # before the GPU is initialised
+            phantom.synth_rf(w0)
+        if not torch.cuda.is_available():
+            print("no GPU visible", file=sys.stderr)
+            sys.exit(1)
+        wf.load()
+        serve_main(args, wf, phantom, torch, np)
         return
 
     w = phantom.get_workload(args.workload)
@@ -266,7 +377,8 @@ def main():
             "peak": round(PEAK_LANE_OPS / 1e12, 2),
             "unit": "Tops/s (vector lane-ops)",
             "frac": round(achieved / PEAK_LANE_OPS, 4),
-            "traffic": None,
+            "traffic": profiled_traffic(w.name),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "ops_per_launch": OPS_PER_CONTRIB * act_frac * nominal,
             "avg_launch_ms": round(das_avg_s * 1e3, 4),
         },

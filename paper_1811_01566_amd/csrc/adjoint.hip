@@ -158,6 +158,7 @@ hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
 
 template <int MODE>
 hipError_t launch_adj_shape(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
+    if (nt == 1024) return launch_adj<MODE, 1024, 2>(a, lds, s);
     if (nt == 512) return launch_adj<MODE, 512, 2>(a, lds, s);
     return px == 4 ? launch_adj<MODE, 256, 4>(a, lds, s) : launch_adj<MODE, 256, 1>(a, lds, s);
 }

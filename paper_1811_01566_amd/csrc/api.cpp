@@ -264,16 +264,17 @@ size_t das_lds_bytes(int slot, int T) {
 constexpr size_t kLdsSoft = 65536;
 constexpr size_t kLdsHard = 163840;
 
-#ifndef WF_DAS_PREFER_512
-#define WF_DAS_PREFER_512 0
+#ifndef WF_DAS_ALLOW_1024
+#define WF_DAS_ALLOW_1024 1
+#endif
+#ifndef WF_DAS_XCD_ORDER
+#define WF_DAS_XCD_ORDER 0
 #endif
 
 bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
     // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
-    // with twice the waves per workgroup
-    const int shapes[3][2] = {{WF_DAS_PREFER_512 ? 512 : 256, WF_DAS_PREFER_512 ? 2 : 4},
-                              {WF_DAS_PREFER_512 ? 256 : 512, WF_DAS_PREFER_512 ? 4 : 2},
-                              {256, 1}};
+    // with twice the waves per workgroup, 1024 x 2 twice the tile
+    const int shapes[4][2] = {{WF_DAS_ALLOW_1024 ? 1024 : 512, 2}, {512, 2}, {256, 4}, {256, 1}};
     for (size_t limit : {kLdsSoft, kLdsHard}) {
         double best_score = -1.0;
         for (const auto& sh : shapes) {
@@ -287,16 +288,20 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
                 const int nst = ((2 * span + 8) + 7) & ~7;
                 const int slot = nst + span + 8;
                 if (nst + span > 511) continue;
-                const int max_groups = nt == 512 ? 2 : wf::kMaxGroups;
+                const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
                 if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
                 const size_t lds = das_lds_bytes(slot, acq->n_tx);
-                if (lds > limit) continue;
+                // a 16-wave workgroup fills its CU alone: no need to leave
+                // LDS for a second one
+                if (lds > (nt == 1024 ? kLdsHard : limit)) continue;
                 const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
                 const double wgs = (double)ntz * ntx * acq->n_frames;
-                // pixels served per staged sample, discounted when the grid is
-                // too small to fill the chip; ties keep the earlier shape
+                // pixels served per staged sample, discounted when there are
+                // too few workgroups to give every CU 16 waves; ties keep the
+                // earlier shape
+                const double fill = 256.0 * 1024.0 / nt;
                 const double reuse = (double)ez * ex / nst;
-                const double score = reuse * std::min(1.0, wgs / 512.0);
+                const double score = reuse * std::min(1.0, wgs / fill);
                 if (score > best_score * (1.0 + 1e-9)) {
                     best_score = score;
                     best->threads = nt;
@@ -348,6 +353,7 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->tz_log2 = tp->tz_log2;
     a->ntz = tp->ntz;
     a->ntx = tp->ntx;
+    a->xcd_order = (WF_DAS_XCD_ORDER && (tp->ntz * tp->ntx) % 8 == 0) ? 1 : 0;
     a->ng = tp->nst / 8;
     a->ng_inv = ((1 << 20) + a->ng - 1) / a->ng;
     a->nst = tp->nst;

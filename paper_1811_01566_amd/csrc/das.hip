@@ -34,10 +34,10 @@
 namespace wf {
 namespace {
 
-#ifndef WF_DAS_JB
-#define WF_DAS_JB 2
+#ifndef WF_DAS_READS
+#define WF_DAS_READS 8
 #endif
-constexpr int kJB = WF_DAS_JB;  // channels per batch of LDS reads
+// LDS reads in flight per lane per batch (channels per batch = this / PX)
 
 // What the gather accumulates per contribution.
 enum : int {
@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             // batches of LDS reads are issued before their FMAs so that
             // several reads are in flight per wave
             const uint32_t base = lds0 + (uint32_t)cur * buf_bytes;
+            constexpr int kJB = (WF_DAS_READS / PX) < 1 ? 1 : (WF_DAS_READS / PX);
 #pragma unroll
             for (int j0 = 0; j0 < kChunk; j0 += kJB) {
                 float2 ed[kJB][PX];
@@ -288,10 +289,12 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     return hipGetLastError();
 }
 
-// (threads, pixels per thread): 256 x 4, 512 x 2 (twice the waves for the
-// same tile) or 256 x 1 (small tiles for coarse grids)
+// (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 512 x 2
+// (8 waves), 256 x 4 (4 waves, the same tile as 512 x 2) or 256 x 1 (small
+// tiles for coarse grids)
 template <int MODE, typename RT, int OP>
 hipError_t launch_px(int nt, int px, int groups, const DasArgs& a, size_t lds, hipStream_t s) {
+    if (nt == 1024) return launch_one<MODE, RT, 1024, 2, 2, OP>(a, lds, s);
     if (nt == 512) return launch_one<MODE, RT, 512, 2, 2, OP>(a, lds, s);
     if (px == 4)
         return groups <= 2 ? launch_one<MODE, RT, 256, 4, 2, OP>(a, lds, s)
@@ -313,7 +316,7 @@ hipError_t launch_mode(int dtype, int nt, int px, int groups, const DasArgs& a, 
 }  // namespace
 
 static bool shape_ok(int nt, int px, int groups) {
-    if (nt == 512) return px == 2 && groups <= 2;
+    if (nt == 1024 || nt == 512) return px == 2 && groups <= 2;
     return nt == 256 && (px == 4 || px == 1) && groups <= kMaxGroups;
 }
 

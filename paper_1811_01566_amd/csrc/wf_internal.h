@@ -43,6 +43,7 @@ struct DasArgs {
     int F, T, C, S, nz, nx;
     int tz_log2;        // tile depth TZ = 1 << tz_log2
     int ntz, ntx;       // tiles along z and x
+    int xcd_order;      // 1: tile order grouped per XCD (tile count % 8 == 0)
     int ng;             // 8-sample groups staged per window (nst / 8)
     int ng_inv;         // ceil(2^20 / ng), exact division for small numerators
     int nst;            // staged entries per window

@@ -33,6 +33,9 @@ if ROOT not in sys.path:
 # lane-instructions per second without packed-FP32 dual issue; the published
 # 157.3 TFLOP/s FP32 vector peak is that rate x 2 (FMA) x 2 (packed).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12  # bytes/s
+# non-packed FP32 fused multiply-add rate: 2 flops per lane-instruction
+PEAK_FMA = 2 * PEAK_LANE_OPS
 # algorithmic lane-ops of one active contribution: transmit + receive delay
 # add, index / fraction split, r[n+1] - r[n], interpolating FMA, accumulate
 OPS_PER_CONTRIB = 5
@@ -326,6 +329,39 @@ def main():
         env_ms.append(e0.elapsed_time(e1))
         logc_ms.append(e1.elapsed_time(e2))
 
+    # ---- FIR pre-filter and qUS moment maps, timed beside the B-mode step -
+    from phantom.configs import FIR_TAPS, QUS_WINDOW
+
+    taps = phantom.workload_taps(w, FIR_TAPS)
+    rf_f = torch.empty(rf.shape, dtype=torch.float32, device=dev)
+    env_buf, _ = wf.envelope(y)
+    q = QUS_WINDOW
+    fir_ms, mom_ms = [], []
+    for i in range(12):
+        e0.record(stream)
+        wf.fir(rf, taps, out=rf_f)
+        e1.record(stream)
+        maps = wf.moments(env_buf, q["wz"], q["wx"], q["sz"], q["sx"])
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if i >= 2:
+            fir_ms.append(e0.elapsed_time(e1))
+            mom_ms.append(e1.elapsed_time(e2))
+    fir_s = float(np.mean(fir_ms)) * 1e-3
+    n_samp = rf.numel()
+    fir_bytes = n_samp * (rf.element_size() + 4)
+    fir_flops = 2.0 * FIR_TAPS * n_samp
+    prefilter = {
+        "fir": {"ms": round(fir_s * 1e3, 4), "taps": FIR_TAPS,
+                "hbm_bytes": fir_bytes, "flops": fir_flops,
+                "hbm_frac": round(fir_bytes / fir_s / PEAK_HBM, 4),
+                "fma_frac": round(fir_flops / fir_s / PEAK_FMA, 4)},
+        "moments": {"ms": round(float(np.mean(mom_ms)), 4), "window": q,
+                    "maps": list(maps.shape),
+                    "hbm_bytes": int(env_buf.numel() * 4 + maps.numel() * 4)},
+    }
+    del rf_f
+
     # ---- closed-loop frame latency: enqueue -> completion, one in flight --
     lat = []
     for _ in range(args.latency_frames):
@@ -382,6 +418,7 @@ def main():
             "ops_per_launch": OPS_PER_CONTRIB * act_frac * nominal,
             "avg_launch_ms": round(das_avg_s * 1e3, 4),
         },
+        "prefilter_and_qus": prefilter,
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:

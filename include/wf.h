@@ -224,6 +224,35 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
                            const int32_t* tx_elem, const double* angles_rad, int32_t tref,
                            const wf_grid* grid, int32_t* info);
 
+/*
+ * FIR pre-filter along samples (the pre-processing op of Sec. II-B): every
+ * record of n_s samples is filtered on its own,
+ *   out[s] = sum_k taps[k] in[s + D - k],  D = (n_taps - 1) / 2,
+ * with in = 0 outside the record, so an odd-length linear-phase filter adds
+ * no delay and the DAS time origin is unchanged.
+ *   rf      DEVICE [n_rec][n_s] of dtype (wf_rf_dtype; int16 and FP16
+ *           convert exactly), 16-byte aligned, n_s % 8 == 0; finite values.
+ *   taps    HOST float [n_taps], n_taps odd, 1..63; read during the call.
+ *   out     DEVICE float [n_rec][n_s], 16-byte aligned, must not overlap rf.
+ * n_rec = 0 does nothing (rf and out may then be NULL).
+ * FP32 fused multiply-adds in tap order.  With rf = RF [F][T][C][S] and
+ * n_rec = F T C the output is RF for the DAS calls with dtype WF_RF_F32.
+ */
+wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, const float* taps,
+                 int32_t n_taps, float* out, void* stream);
+
+/*
+ * Windowed moments of the envelope (the qUS estimator's inputs, Fig. 3:
+ * slice -> E[X], E[X^2], E[X^3]): windows of wz x wx samples at origins
+ * (i sz, j sx), whole windows only, mz = (nz - wz) / sz + 1 and
+ * mx = (nx - wx) / sx + 1; E[X^p] is the mean of env^p over the window.
+ *   env  DEVICE float [F][nz][nx] (the linear envelope, e.g. wf_envelope's).
+ *   out  DEVICE float [F][3][mz][mx] (p = 1, 2, 3); must not overlap env.
+ * 1 <= wz <= nz, 1 <= wx <= nx, sz, sx >= 1, nx <= 4096.  Deterministic.
+ */
+wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx, int32_t wz,
+                     int32_t wx, int32_t sz, int32_t sx, float* out, void* stream);
+
 /* Message of the last failed call on this thread ("" after success). */
 const char* wf_last_error(void);
 

@@ -9,7 +9,9 @@ not on a GPU.
 Pipeline (paper Fig. 2): :func:`das_stai` / :func:`das_pwi` (Beamforming,
 Sec. II-B) -> :func:`envelope` (Analytic Signal + Absolute Value) ->
 :func:`log_compress` (Dynamic Adjustment, dB clip of Sec. III); :func:`bmode`
-runs the last two.
+runs the last two.  Around it: :func:`fir` (the FIR pre-filter of the RF,
+Sec. II-B) and :func:`moments` (windowed E[X], E[X^2], E[X^3] of the
+envelope, the qUS estimator's inputs, Fig. 3).
 """
 
 from __future__ import annotations
@@ -288,6 +290,42 @@ def bmode(bf, dr_db: float, offset: bool = False, out=None, col_max=None, stream
 # ---------------------------------------------------------------------------
 # derivatives (adjoint w.r.t. RF, forward-mode d y / d c) and autograd
 # ---------------------------------------------------------------------------
+
+def fir(rf, taps: Sequence[float], out=None, stream=None):
+    """FIR along the last (sample) axis of rf [..., S] (int16, float16 or
+    float32), centred ('same' alignment, odd tap count <= 63); returns float32
+    of rf's shape."""
+    torch = _torch()
+    lib = load()
+    taps = [float(v) for v in taps]
+    n_s = int(rf.shape[-1])
+    n_rec = int(rf.numel() // n_s) if n_s else 0
+    if out is None:
+        out = torch.empty(rf.shape, dtype=torch.float32, device=rf.device)
+    h = (ctypes.c_float * max(1, len(taps)))(*taps)
+    _lib.check(lib.wf_fir(_dev(rf, "rf"), _rf_dtype(rf), n_rec, n_s, h, len(taps),
+                          _dev(out, "out"), _stream_ptr(rf, stream)), "wf_fir")
+    return out
+
+
+def moments(env, wz: int, wx: int, sz: int, sx: int, out=None, stream=None):
+    """Windowed moments of env [F][nz][nx] (or [nz][nx]): returns
+    [F][3][mz][mx] (or [3][mz][mx]) holding E[X], E[X^2], E[X^3] of the
+    wz x wx windows at origins (i sz, j sx)."""
+    torch = _torch()
+    lib = load()
+    squeeze = env.dim() == 2
+    e3 = env.unsqueeze(0) if squeeze else env
+    nf, nz, nx = e3.shape
+    if not (1 <= wz <= nz and 1 <= wx <= nx and sz >= 1 and sx >= 1):
+        raise ValueError(f"window {wz}x{wx} / strides {sz},{sx} do not fit {nz}x{nx}")
+    mz, mx = (nz - wz) // sz + 1, (nx - wx) // sx + 1
+    if out is None:
+        out = torch.empty((nf, 3, mz, mx), dtype=torch.float32, device=env.device)
+    _lib.check(lib.wf_moments(_dev(e3, "env"), nf, nz, nx, int(wz), int(wx), int(sz), int(sx),
+                              _dev(out, "out"), _stream_ptr(e3, stream)), "wf_moments")
+    return out[0] if squeeze else out
+
 
 def _mode_args(scan: Scan, keep: _Keep):
     mode = 0 if scan.mode == "stai" else 1

@@ -58,6 +58,8 @@ SIGNATURES = {
     "wf_envelope": (I, [V, I, I, I, V, V, V]),
     "wf_log_compress": (I, [V, V, I, I, I, F, I, V, V]),
     "wf_bmode": (I, [V, I, I, I, F, I, V, V, V]),
+    "wf_fir": (I, [V, I, ctypes.c_int64, I, ctypes.POINTER(ctypes.c_float), I, V, V]),
+    "wf_moments": (I, [V, I, I, I, I, I, I, I, V, V]),
     "wf_last_error": (ctypes.c_char_p, []),
     "wf_abi_version": (I, []),
     "wf_geometry_cache_clear": (I, []),

@@ -607,6 +607,55 @@ wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx, fl
     return wf_log_compress(out_db, col_max, n_frames, nz, nx, dr_db, flags, out_db, stream);
 }
 
+wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, const float* taps,
+                 int32_t n_taps, float* out, void* stream) {
+    if (!taps) return fail(WF_ERR_INVALID_ARG, "taps is NULL");
+    if (dtype < WF_RF_I16 || dtype > WF_RF_F32)
+        return fail(WF_ERR_INVALID_ARG, "dtype=%d is not a wf_rf_dtype", dtype);
+    if (n_rec < 0) return fail(WF_ERR_INVALID_ARG, "n_rec=%lld is negative", (long long)n_rec);
+    if (n_s <= 0 || n_s % 8 != 0)
+        return fail(WF_ERR_UNSUPPORTED, "n_s=%d must be a positive multiple of 8", n_s);
+    if (n_taps < 1 || n_taps > 63 || n_taps % 2 != 1)
+        return fail(WF_ERR_UNSUPPORTED, "n_taps=%d must be odd, 1..63", n_taps);
+    for (int k = 0; k < n_taps; ++k)
+        if (!std::isfinite(taps[k])) return fail(WF_ERR_INVALID_ARG, "taps[%d] is not finite", k);
+    if (n_rec == 0) return ok();  // nothing to filter; rf and out may be NULL
+    if (!rf || !out) return fail(WF_ERR_INVALID_ARG, "rf and out must not be NULL");
+    if (((uintptr_t)rf & 15) || ((uintptr_t)out & 15))
+        return fail(WF_ERR_UNSUPPORTED, "rf and out must be 16-byte aligned");
+    const size_t esz = dtype == WF_RF_F32 ? 4 : 2;
+    if (n_rec > (1LL << 36) / n_s) return fail(WF_ERR_INVALID_ARG, "RF too large");
+    const long long total = (long long)n_rec * n_s;
+    if (overlaps(rf, (size_t)total * esz, out, (size_t)total * 4))
+        return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
+    wf::FirTaps h{};
+    const int kp = n_taps <= 15 ? 15 : (n_taps <= 31 ? 31 : 63);
+    const int pad = (kp - n_taps) / 2;
+    for (int k = 0; k < n_taps; ++k) h.h[pad + k] = taps[k];
+    hipError_t e = wf::launch_fir(dtype, rf, total, n_s, kp, h, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "FIR kernel launch");
+    return ok();
+}
+
+wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx, int32_t wz,
+                     int32_t wx, int32_t sz, int32_t sx, float* out, void* stream) {
+    wf_status st = check_image(env, n_frames, nz, nx, "env");
+    if (st != WF_OK) return st;
+    if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
+    if (nx > 4096) return fail(WF_ERR_UNSUPPORTED, "nx=%d is above 4096", nx);
+    if (wz < 1 || wz > nz || wx < 1 || wx > nx)
+        return fail(WF_ERR_INVALID_ARG, "window %dx%d does not fit the %dx%d frame", wz, wx, nz,
+                    nx);
+    if (sz < 1 || sx < 1) return fail(WF_ERR_INVALID_ARG, "strides must be >= 1");
+    const int mz = (nz - wz) / sz + 1, mx = (nx - wx) / sx + 1;
+    if (overlaps(env, (size_t)n_frames * nz * nx * 4, out, (size_t)n_frames * 3 * mz * mx * 4))
+        return fail(WF_ERR_INVALID_ARG, "out overlaps env");
+    hipError_t e = wf::launch_moments(env, n_frames, nz, nx, wz, wx, sz, sx, mz, mx, out,
+                                      (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
+    return ok();
+}
+
 wf_status wf_geometry_cache_clear(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     hipError_t first = hipSuccess;

@@ -1,0 +1,222 @@
+// FIR pre-filter along samples (K0) and windowed envelope moments (K6) for
+// gfx950.
+//
+// K0 (pre-processing FIR, Sec. II-B list of ops).  Every record of S samples
+// (one channel of one transmit of one frame) is filtered on its own:
+//   y[s] = sum_k h[k] r[s + D - k],  D = (K - 1) / 2,  r = 0 outside [0, S),
+// so an odd-length linear-phase filter adds no delay.  The records are
+// contiguous, so the whole RF array is one flat sequence: a workgroup
+// filters 2048 consecutive outputs, staging them plus a 32-sample halo on
+// each side in LDS as FP32 (int16 and FP16 convert exactly).  A lane owns 8
+// consecutive outputs - S % 8 == 0 keeps them inside one record - reads its
+// K + 7 inputs from LDS into registers with 16-byte reads, zeroes the ones
+// that fall in a neighbouring record (only lanes within D of a record edge
+// do this), and runs 8 K FMAs with the taps in scalar registers.  The tap
+// count is padded to KP in {15, 31, 63} with zeros placed symmetrically,
+// which adds exact zeros to the sums.  Per output: K FMAs, 2-4 bytes read
+// and 4 written; at K = 31 the vector-FMA and HBM times are about equal.
+//
+// K6 (qUS moment maps, Fig. 3: slice -> E[X], E[X^2], E[X^3]).  Window
+// wz x wx at origins (i sz, j sx), whole windows only.  One workgroup per
+// (window row i, frame): the lanes first sum env, env^2, env^3 down the wz
+// rows of every needed column (reads coalesced along x), keep the column
+// sums in LDS, then each lane adds wx column sums for its windows and
+// divides by wz wx.  Fixed summation order: deterministic.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "wf_internal.h"
+
+namespace wf {
+namespace {
+
+constexpr int kFirThreads = 256;
+constexpr int kFirPerLane = 8;
+constexpr int kFirBlock = kFirThreads * kFirPerLane;  // outputs per workgroup
+constexpr int kFirHalo = 32;                           // >= D for KP <= 63
+
+template <typename RT>
+__device__ __forceinline__ void load8(const RT* p, float (&v)[8]);
+
+template <>
+__device__ __forceinline__ void load8<int16_t>(const int16_t* p, float (&v)[8]) {
+    const int4 q = *reinterpret_cast<const int4*>(p);
+    const int w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[2 * i] = (float)(int16_t)(w[i] & 0xFFFF);
+        v[2 * i + 1] = (float)(w[i] >> 16);
+    }
+}
+
+template <>
+__device__ __forceinline__ void load8<__half>(const __half* p, float (&v)[8]) {
+    const int4 q = *reinterpret_cast<const int4*>(p);
+    const int w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[2 * i] = __half2float(__ushort_as_half((unsigned short)(w[i] & 0xFFFF)));
+        v[2 * i + 1] = __half2float(__ushort_as_half((unsigned short)((unsigned)w[i] >> 16)));
+    }
+}
+
+template <>
+__device__ __forceinline__ void load8<float>(const float* p, float (&v)[8]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+template <typename RT, int KP>
+__global__ void __launch_bounds__(kFirThreads)
+    fir_kernel(const RT* __restrict__ rf, float* __restrict__ out, long long total, int S,
+               const FirTaps taps) {
+    constexpr int D = (KP - 1) / 2;
+    constexpr int kStage = kFirBlock + 2 * kFirHalo;
+    // the lane's inputs start at LDS entry 8 lane + kFirHalo - D; read the
+    // 16-byte-aligned superset
+    constexpr int kLead = (kFirHalo - D) & 3;
+    constexpr int kFirst = (kFirHalo - D) - kLead;
+    constexpr int kWin = KP + kFirPerLane - 1;             // inputs a lane needs
+    constexpr int kRead = (kLead + kWin + 3) / 4;          // float4 reads
+    __shared__ __align__(16) float xs[kStage];
+
+    const int tid = threadIdx.x;
+    const long long base = (long long)blockIdx.x * kFirBlock;
+    // ---- stage [base - halo, base + block + halo) as FP32, zeros outside ----
+    for (int c = tid; c < kStage / 8; c += kFirThreads) {
+        const long long q = base - kFirHalo + 8LL * c;  // multiple of 8
+        float v[8];
+        if (q >= 0 && q < total) {
+            load8<RT>(rf + q, v);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+        }
+        float4* d = reinterpret_cast<float4*>(xs + 8 * c);
+        d[0] = make_float4(v[0], v[1], v[2], v[3]);
+        d[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+    __syncthreads();
+
+    const long long p0 = base + (long long)kFirPerLane * tid;
+    if (p0 >= total) return;
+    float xw[kRead * 4];
+    const float4* src = reinterpret_cast<const float4*>(xs + kFirPerLane * tid + kFirst);
+#pragma unroll
+    for (int r = 0; r < kRead; ++r) {
+        const float4 q = src[r];
+        xw[4 * r] = q.x;
+        xw[4 * r + 1] = q.y;
+        xw[4 * r + 2] = q.z;
+        xw[4 * r + 3] = q.w;
+    }
+    // input m (record position s0 - D + m) sits at xw[kLead + m]; zero the
+    // ones outside this record
+    const int s0 = (int)(p0 % S);
+    if (s0 < D || s0 + kFirPerLane + D > S) {
+        const int lo = D - s0;      // m < lo: before the record
+        const int hi = S - s0 + D;  // m >= hi: after it
+#pragma unroll
+        for (int m = 0; m < kWin; ++m)
+            if (m < lo || m >= hi) xw[kLead + m] = 0.0f;
+    }
+    float acc[kFirPerLane];
+#pragma unroll
+    for (int i = 0; i < kFirPerLane; ++i) acc[i] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const float h = taps.h[k];
+#pragma unroll
+        for (int i = 0; i < kFirPerLane; ++i)
+            acc[i] = fmaf(h, xw[kLead + i + KP - 1 - k], acc[i]);
+    }
+    float4* dst = reinterpret_cast<float4*>(out + p0);
+    dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+}
+
+template <typename RT>
+hipError_t launch_fir_t(const RT* rf, long long total, int S, int kp, const FirTaps& taps,
+                        float* out, hipStream_t s) {
+    const long long blocks = (total + kFirBlock - 1) / kFirBlock;
+    const dim3 grid((unsigned)blocks);
+    if (kp == 15)
+        hipLaunchKernelGGL((fir_kernel<RT, 15>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+                           taps);
+    else if (kp == 31)
+        hipLaunchKernelGGL((fir_kernel<RT, 31>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+                           taps);
+    else
+        hipLaunchKernelGGL((fir_kernel<RT, 63>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+                           taps);
+    return hipGetLastError();
+}
+
+constexpr int kMomThreads = 256;
+
+__global__ void __launch_bounds__(kMomThreads)
+    moments_kernel(const float* __restrict__ env, float* __restrict__ out, int nz, int nx,
+                   int wz, int wx, int sz, int sx, int mz, int mx) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int i = blockIdx.x;
+    const int f = blockIdx.y;
+    const int ncol = (mx - 1) * sx + wx;  // columns some window uses
+    float* v1 = reinterpret_cast<float*>(smem);
+    float* v2 = v1 + ncol;
+    float* v3 = v2 + ncol;
+    const float* e = env + ((size_t)f * nz + (size_t)i * sz) * nx;
+    for (int x = threadIdx.x; x < ncol; x += kMomThreads) {
+        float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        for (int z = 0; z < wz; ++z) {
+            const float v = e[(size_t)z * nx + x];
+            const float q = v * v;
+            s1 += v;
+            s2 += q;
+            s3 += q * v;
+        }
+        v1[x] = s1;
+        v2[x] = s2;
+        v3[x] = s3;
+    }
+    __syncthreads();
+    const float cnt = (float)wz * (float)wx;
+    const size_t plane = (size_t)mz * mx;
+    float* o = out + (size_t)f * 3 * plane + (size_t)i * mx;
+    for (int j = threadIdx.x; j < mx; j += kMomThreads) {
+        float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+        const int x0 = j * sx;
+        for (int x = x0; x < x0 + wx; ++x) {
+            a1 += v1[x];
+            a2 += v2[x];
+            a3 += v3[x];
+        }
+        o[j] = a1 / cnt;
+        o[plane + j] = a2 / cnt;
+        o[2 * plane + j] = a3 / cnt;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fir(int dtype, const void* rf, long long total, int S, int kp,
+                      const FirTaps& taps, float* out, hipStream_t s) {
+    switch (dtype) {
+        case 0: return launch_fir_t(static_cast<const int16_t*>(rf), total, S, kp, taps, out, s);
+        case 1: return launch_fir_t(static_cast<const __half*>(rf), total, S, kp, taps, out, s);
+        default: return launch_fir_t(static_cast<const float*>(rf), total, S, kp, taps, out, s);
+    }
+}
+
+hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int wx, int sz,
+                          int sx, int mz, int mx, float* out, hipStream_t s) {
+    const size_t lds = 3 * sizeof(float) * (size_t)((mx - 1) * sx + wx);
+    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)mz, (unsigned)F), dim3(kMomThreads), lds, s,
+                       env, out, nz, nx, wz, wx, sz, sx, mz, mx);
+    return hipGetLastError();
+}
+
+}  // namespace wf

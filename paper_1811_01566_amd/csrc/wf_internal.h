@@ -74,6 +74,11 @@ struct DelayArgs {
     const ChConst* ch_tab;
 };
 
+// FIR taps, zero-padded symmetrically to the kernel's tap count (15, 31, 63).
+struct FirTaps {
+    float h[64];
+};
+
 // Launchers; return the hipError_t of the launch.
 hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
                       size_t lds_bytes, hipStream_t s);
@@ -88,5 +93,9 @@ hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, f
                            hipStream_t s);
 hipError_t launch_log_compress(const float* env, const float* col_max, int F, int nz, int nx,
                                float dr_db, int offset, float* out, hipStream_t s);
+hipError_t launch_fir(int dtype, const void* rf, long long total, int S, int kp,
+                      const FirTaps& taps, float* out, hipStream_t s);
+hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int wx, int sz,
+                          int sx, int mz, int mx, float* out, hipStream_t s);
 
 }  // namespace wf

@@ -21,8 +21,11 @@ from .configs import (
     tiny_pwi,
 )
 from .synth import synth_rf, scatterers_for, point_echo_rf
+from .taps import bandpass_taps, workload_taps
 
 __all__ = [
+    "bandpass_taps",
+    "workload_taps",
     "Workload",
     "WORKLOADS",
     "get_workload",

@@ -264,3 +264,10 @@ def served_pool(n_classes: int = 16, seed: int = 7, n_points: int = 24) -> Seque
         zs = tuple(pr.uniform(6e-3, 29e-3) for _ in range(n_points))
         out.append(w.with_(phantom="points", phantom_args=dict(x=xs, z=zs), seed=seed + k))
     return out
+
+
+# qUS moment maps of the envelope: window 32 depth samples (about three pulse
+# lengths on the 1024-row grids) x 8 columns, strides 8 x 2 (75 % overlap)
+QUS_WINDOW = dict(wz=32, wx=8, sz=8, sx=2)
+# FIR pre-filter: 31-tap Hamming band-pass over [0.5 fc, 1.5 fc]
+FIR_TAPS = 31

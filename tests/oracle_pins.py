@@ -22,6 +22,8 @@ from oracle import dbclip as B
 from oracle import das as D
 from oracle import adjoint as A
 from oracle import analytic as E
+from oracle import fir as F
+from oracle import moments as M
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -375,6 +377,119 @@ def pin_dydc_linear_ramp():
         _close(got, fd, rtol=1e-6, msg=f"dy/dc ramp vs central difference {w.name}")
 
 
+# --------------------------------------------------------------------------
+# FIR pre-filter (Sec. II-B pre-processing op)
+# --------------------------------------------------------------------------
+
+def pin_fir_impulse_and_numpy():
+    rng = np.random.default_rng(31)
+    for k_len in (1, 7, 31):
+        h = rng.normal(size=k_len)  # no symmetry: a reversed filter fails
+        d = (k_len - 1) // 2
+        x = np.zeros(96)
+        x[40] = 1.0
+        y = F.fir_same(x, h)
+        # an impulse at s0 returns the taps at s0 - D ... s0 + D, zeros elsewhere
+        exp = np.zeros(96)
+        exp[40 - d:40 + d + 1] = h
+        _close(y, exp, rtol=0, atol=1e-15, msg=f"fir impulse K={k_len}")
+        # the definition is numpy's centred convolution, rows filtered separately
+        r = rng.normal(size=(3, 2, 64))
+        got = F.fir_same(r, h)
+        ref = np.stack([[np.convolve(r[a, b], h, mode="same") for b in range(2)]
+                        for a in range(3)])
+        _close(got, ref, rtol=1e-12, atol=1e-12, msg=f"fir vs numpy.convolve K={k_len}")
+
+
+def pin_fir_moving_average_tone():
+    # K-tap moving average of a tone: gain sin(pi f K / fs) / (K sin(pi f / fs))
+    # (Dirichlet kernel), zero phase for the centred filter, away from edges
+    k_len, fs, f0, s_len = 9, 50e6, 3.1e6, 400
+    h = np.full(k_len, 1.0 / k_len)
+    s = np.arange(s_len)
+    x = np.cos(2 * np.pi * f0 * s / fs + 0.4)
+    gain = math.sin(math.pi * f0 * k_len / fs) / (k_len * math.sin(math.pi * f0 / fs))
+    y = F.fir_same(x, h)
+    d = (k_len - 1) // 2
+    _close(y[d:s_len - d], gain * x[d:s_len - d], rtol=0, atol=1e-12, msg="fir tone gain")
+
+
+def pin_fir_edges_constant():
+    # r = 1: y[s] is the sum of the taps that land inside the record; with
+    # h[k] = k + 1 the partial sums are arithmetic series
+    k_len, s_len = 11, 40
+    d = (k_len - 1) // 2
+    h = np.arange(1, k_len + 1, dtype=np.float64)
+    y = F.fir_same(np.ones(s_len), h)
+    total = k_len * (k_len + 1) / 2
+    for s in range(s_len):
+        # taps k with 0 <= s + d - k < S  <=>  s + d - S < k <= s + d
+        k_hi = min(k_len - 1, s + d)
+        k_lo = max(0, s + d - s_len + 1)
+        exp = (k_hi + 1) * (k_hi + 2) / 2 - k_lo * (k_lo + 1) / 2
+        assert abs(y[s] - exp) <= 1e-12, f"fir edge s={s}: {y[s]} vs {exp}"
+    assert abs(y[s_len // 2] - total) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# qUS moment maps (Fig. 3: slice -> E[X], E[X^2], E[X^3])
+# --------------------------------------------------------------------------
+
+def pin_moments_constant_and_depth_ramp():
+    env = np.full((2, 20, 12), 1.5)
+    m = M.moment_maps(env, 5, 3, 2, 4)
+    assert m.shape == (2, 3, 8, 3)
+    for p in range(3):
+        _close(m[:, p], np.full((2, 8, 3), 1.5 ** (p + 1)), rtol=1e-14, msg="moments constant")
+    # env = depth index z: window rows a..a+wz-1, Faulhaber sums of z, z^2, z^3
+    nz, nx, wz, wx, sz, sx = 23, 9, 6, 4, 3, 2
+    env = np.broadcast_to(np.arange(nz, dtype=np.float64)[:, None], (nz, nx)).copy()
+    m = M.moment_maps(env, wz, wx, sz, sx)
+    mz, mx = (nz - wz) // sz + 1, (nx - wx) // sx + 1
+    assert m.shape == (3, mz, mx)
+
+    def s_pow(n, p):  # sum_{z=0}^{n-1} z^p
+        return [n, n * (n - 1) / 2, (n - 1) * n * (2 * n - 1) / 6, ((n - 1) * n / 2) ** 2][p]
+
+    for i in range(mz):
+        a = i * sz
+        for p in (1, 2, 3):
+            exp = (s_pow(a + wz, p) - s_pow(a, p)) / wz
+            _close(m[p - 1, i], np.full(mx, exp), rtol=1e-13, msg=f"moments ramp p={p} i={i}")
+
+
+def pin_moments_lateral_index_and_brute():
+    rng = np.random.default_rng(32)
+    # env = lateral index x: E[X] of window j is j sx + (wx - 1) / 2
+    env = np.broadcast_to(np.arange(17, dtype=np.float64)[None, :], (8, 17)).copy()
+    m = M.moment_maps(env, 3, 5, 1, 3)
+    exp = np.arange(m.shape[2]) * 3 + 2.0
+    _close(m[0], np.broadcast_to(exp, m[0].shape), rtol=1e-14, msg="moments lateral placement")
+    # brute force, scalar loops
+    env = rng.rayleigh(1.0, size=(2, 11, 10))
+    wz, wx, sz, sx = 4, 3, 3, 2
+    got = M.moment_maps(env, wz, wx, sz, sx)
+    for f in range(2):
+        for i in range((11 - wz) // sz + 1):
+            for j in range((10 - wx) // sx + 1):
+                vals = [env[f, i * sz + a, j * sx + b] for a in range(wz) for b in range(wx)]
+                for p in (1, 2, 3):
+                    exp = sum(v ** p for v in vals) / len(vals)
+                    assert abs(got[f, p - 1, i, j] - exp) <= 1e-12 * max(1.0, exp)
+
+
+def pin_moments_rayleigh():
+    # envelope of circular complex Gaussian speckle: Rayleigh(sigma) with
+    # E[X] = sigma sqrt(pi/2), E[X^2] = 2 sigma^2, E[X^3] = 3 sigma^3 sqrt(pi/2)
+    rng = np.random.default_rng(33)
+    sigma = 0.7
+    z = rng.normal(0, sigma, size=(512, 512)) + 1j * rng.normal(0, sigma, size=(512, 512))
+    m = M.moment_maps(np.abs(z), 256, 256, 256, 256)
+    exp = (sigma * math.sqrt(math.pi / 2), 2 * sigma ** 2, 3 * sigma ** 3 * math.sqrt(math.pi / 2))
+    for p in range(3):
+        _close(m[p], np.full((2, 2), exp[p]), rtol=0.02, msg=f"Rayleigh moment {p + 1}")
+
+
 ALL_PINS = [
     pin_tof_golden,
     pin_pwi_wavefront_geometry,
@@ -393,4 +508,10 @@ ALL_PINS = [
     pin_bmode_per_frame_and_degenerate,
     pin_adjoint_dot_product,
     pin_dydc_linear_ramp,
+    pin_fir_impulse_and_numpy,
+    pin_fir_moving_average_tone,
+    pin_fir_edges_constant,
+    pin_moments_constant_and_depth_ramp,
+    pin_moments_lateral_index_and_brute,
+    pin_moments_rayleigh,
 ]

@@ -12,6 +12,8 @@ from oracle import adjoint as A
 from oracle import analytic as E
 from oracle import das as D
 from oracle import dbclip as B
+from oracle import fir as F
+from oracle import moments as M
 
 _orig_interp = D.interp_linear
 _orig_tof_rx = D.tof_receive
@@ -156,6 +158,59 @@ def _dydc_rx_only(rf, tau_tx, tau_rx, weight, t0, fs, c):
 _orig_dydc = A.das_dydc_sum
 
 
+_orig_fir = F.fir_same
+_orig_moments = M.moment_maps
+
+
+def _fir_correlation(rf, taps):
+    # correlates instead of convolving (reversed taps)
+    return _orig_fir(rf, np.asarray(taps, dtype=np.float64)[::-1])
+
+
+def _fir_shift_one(rf, taps):
+    y = _orig_fir(rf, taps)
+    out = np.zeros_like(y)
+    out[..., 1:] = y[..., :-1]
+    return out
+
+
+def _fir_circular(rf, taps):
+    # wraps around the record instead of zero padding
+    h = np.asarray(taps, dtype=np.float64)
+    r = np.asarray(rf, dtype=np.float64)
+    d = (h.shape[0] - 1) // 2
+    return sum(h[k] * np.roll(r, k - d, axis=-1) for k in range(h.shape[0]))
+
+
+def _fir_last_tap_dropped(rf, taps):
+    h = np.array(taps, dtype=np.float64)
+    h[-1] = 0.0
+    return _orig_fir(rf, h)
+
+
+def _moments_cube_of_mean(env, wz, wx, sz, sx):
+    m = _orig_moments(env, wz, wx, sz, sx)
+    m[..., 2, :, :] = m[..., 0, :, :] ** 3
+    return m
+
+
+def _moments_short_window(env, wz, wx, sz, sx):
+    # averages one row fewer than the window
+    e = np.asarray(env, dtype=np.float64)
+    m = _orig_moments(e, max(1, wz - 1), wx, sz, sx)
+    mz = (e.shape[-2] - wz) // sz + 1
+    return m[..., :mz, :]
+
+
+def _moments_swapped_window(env, wz, wx, sz, sx):
+    e = np.asarray(env, dtype=np.float64)
+    return np.swapaxes(_orig_moments(np.swapaxes(e, -1, -2), wz, wx, sz, sx), -1, -2)
+
+
+def _moments_unit_stride(env, wz, wx, sz, sx):
+    return _orig_moments(env, wz, wx, 1, 1)
+
+
 MUTATIONS = {
     "interp_floor_only": (D, "interp_linear", _interp_floor_only),
     "interp_swapped_weights": (D, "interp_linear", _interp_swapped_weights),
@@ -175,6 +230,14 @@ MUTATIONS = {
     "db_no_clip": (B, "log_compress", _logc_no_clip),
     "adjoint_weight_not_alpha": (A, "das_adjoint_sum", _adjoint_no_alpha),
     "dydc_sign": (A, "das_dydc_sum", _dydc_sign),
+    "fir_correlation_not_convolution": (F, "fir_same", _fir_correlation),
+    "fir_output_shifted": (F, "fir_same", _fir_shift_one),
+    "fir_circular_edges": (F, "fir_same", _fir_circular),
+    "fir_last_tap_dropped": (F, "fir_same", _fir_last_tap_dropped),
+    "moments_cube_of_mean": (M, "moment_maps", _moments_cube_of_mean),
+    "moments_short_window": (M, "moment_maps", _moments_short_window),
+    "moments_window_transposed": (M, "moment_maps", _moments_swapped_window),
+    "moments_stride_ignored": (M, "moment_maps", _moments_unit_stride),
 }
 
 

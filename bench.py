@@ -217,6 +217,10 @@ def serve_main(args, wf, phantom, torch, np):
     plain = latency_stats(run_plain(reqs))
     ok = all(torch.equal(a.image, b.image) for a, b in
              zip(srv.run_trace(reqs[:64]), run_plain(reqs[:64])))
+    # saturation: the same requests all arriving at once
+    burst = [Request(r.rid, r.scan, r.rf, 0.0, r.dr_db) for r in reqs[: min(600, len(reqs))]]
+    served_sat = latency_stats(srv.run_trace(burst))["throughput_rps"]
+    plain_sat = latency_stats(run_plain(burst))["throughput_rps"]
     res = {
         "metric": "B-mode frames/s + DAS Gsamples/s (PWI 128ch×64tx); p99 frame latency",
         "value": round(served["throughput_rps"], 2), "unit": "frames/s",
@@ -229,6 +233,8 @@ def serve_main(args, wf, phantom, torch, np):
                    "streams": 4, "hbm_budget_bytes": budget, "graphs": True},
         "served": served, "plain": plain,
         "plain_capacity_fps": capacity, "arrival_rate_hz": rate,
+        "saturation_fps": {"served": round(served_sat, 2), "plain": round(plain_sat, 2),
+                           "requests": len(burst)},
         "served_equals_plain_bitwise": bool(ok),
         "executors_built": srv.executors_built, "max_in_flight": srv.max_inflight,
     }

@@ -229,6 +229,18 @@ struct PixelSet {
     int iz[PX], ix[PX];
 };
 
+// Pixel q = k NT + thread of the tile.  With WF_DAS_PATCH_LANES, each group
+// of 16 lanes covers a 4 x 4 pixel patch (a wave: 16 deep x 4 wide, or 8 x 8
+// in 8-deep tiles) instead of 16 consecutive rows of one column: the window
+// entries one 16-lane group reads then span about 3 (dz + dx) samples
+// instead of 15 dz, which keeps them in distinct LDS banks.  Pixel k of a
+// lane stays k NT / TZ columns right of pixel 0 (the PWI transmit delay
+// relies on it), and every pixel keeps its own accumulation order, so the
+// output does not depend on the mapping.
+#ifndef WF_DAS_PATCH_LANES
+#define WF_DAS_PATCH_LANES 0
+#endif
+
 template <int NT, int PX>
 __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
                                           PixelSet<PX>& p) {
@@ -236,8 +248,20 @@ __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const int q = k * NT + (int)threadIdx.x;
-        const int qzi = q & (TZ - 1);
-        const int qxi = q >> a.tz_log2;
+        int qzi, qxi;
+        if (WF_DAS_PATCH_LANES) {
+            const int l = q & 63, w = q >> 6;
+            const int wz_log2 = a.tz_log2 >= 4 ? 4 : 3;  // wave slot 16 x 4 or 8 x 8
+            const int lz = wz_log2 == 4 ? ((l & 3) | ((l >> 4) << 2))
+                                        : ((l & 3) | (((l >> 4) & 1) << 2));
+            const int lx = wz_log2 == 4 ? ((l >> 2) & 3) : (((l >> 2) & 3) | ((l >> 5) << 2));
+            const int nzs_log2 = a.tz_log2 - wz_log2;  // wave slots down a tile column
+            qzi = ((w & ((1 << nzs_log2) - 1)) << wz_log2) + lz;
+            qxi = ((w >> nzs_log2) << (6 - wz_log2)) + lx;
+        } else {
+            qzi = q & (TZ - 1);
+            qxi = q >> a.tz_log2;
+        }
         const int iz = g.iz0 + qzi, ix = g.ix0 + qxi;
         p.iz[k] = iz;
         p.ix[k] = ix;

@@ -238,7 +238,7 @@ struct PixelSet {
 // relies on it), and every pixel keeps its own accumulation order, so the
 // output does not depend on the mapping.
 #ifndef WF_DAS_PATCH_LANES
-#define WF_DAS_PATCH_LANES 0
+#define WF_DAS_PATCH_LANES 1
 #endif
 
 template <int NT, int PX>

@@ -140,6 +140,7 @@ struct Geometry {
     std::vector<wf::ChConst> ch;
     float2 Z0, dZ, dX, O;
     float x0f, dxf, fnum2;
+    float dxq;        // 2^g: grid of the hi parts of lateral offsets (samples)
     double dzs, dxs;  // |dz|, |dx| in samples
 };
 
@@ -159,10 +160,29 @@ void build_geometry(int mode, const wf_probe* probe, const wf_acq* acq, const in
     g->fnum2 = (float)(2.0 * acq->f_number);
     g->dzs = std::fabs(grid->dz * k);
     g->dxs = std::fabs(grid->dx * k);
+    // Lateral offsets x - x_e (samples) are split as hi + lo with hi on a
+    // grid 2^-g so coarse that every offset of a grid column from an element
+    // in use, and every column offset from column 0, stays below 2^(23 - g):
+    // then channel and pixel hi parts add exactly on the device.
+    double xmax = std::fabs((grid->nx - 1) * grid->dx * k);
+    auto widen = [&](double xe) {
+        xmax = std::max(xmax, std::fabs((grid->x0 - xe) * k));
+        xmax = std::max(xmax, std::fabs((grid->x0 + (grid->nx - 1) * grid->dx - xe) * k));
+    };
+    for (int j = 0; j < acq->n_ch; ++j) widen(ex[acq->rx_elem ? acq->rx_elem[j] : j]);
+    if (mode == 0)
+        for (int t = 0; t < acq->n_tx; ++t) widen(ex[tx_elem ? tx_elem[t] : t]);
+    const int gexp = std::max(0, std::min(20, 23 - (int)std::ceil(std::log2(xmax + 2.0))));
+    const double gq = std::ldexp(1.0, gexp);
+    g->dxq = (float)gq;
+    auto split_grid = [&](double v) {
+        const double h = std::nearbyint(v * gq) / gq;
+        return make_float2((float)h, (float)(v - h));
+    };
     g->ch.resize(acq->n_ch);
     for (int j = 0; j < acq->n_ch; ++j) {
         const double xe = ex[acq->rx_elem ? acq->rx_elem[j] : j];
-        const float2 d = split((grid->x0 - xe) * k);
+        const float2 d = split_grid((grid->x0 - xe) * k);
         g->ch[j] = make_float4(d.x, d.y, (float)(xe * k), 0.0f);
     }
     g->tx.resize(acq->n_tx);
@@ -170,7 +190,7 @@ void build_geometry(int mode, const wf_probe* probe, const wf_acq* acq, const in
         wf::TxConst tc{};
         if (mode == 0) {
             const double xe = ex[tx_elem ? tx_elem[t] : t];
-            const float2 d = split((grid->x0 - xe) * k);
+            const float2 d = split_grid((grid->x0 - xe) * k);
             tc.v0 = make_float4(d.x, d.y, (float)(xe * k), 0.0f);
             tc.v1 = make_float4(0, 0, 0, 0);
         } else {
@@ -365,6 +385,8 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->dX = g.dX;
     a->O = g.O;
     a->fnum2 = g.fnum2;
+    a->dxq = g.dxq;
+    a->inv_dxq = 1.0f / g.dxq;
     a->x0f = g.x0f;
     a->dxf = g.dxf;
     a->t0fs = (float)(acq->t0 * acq->fs);
@@ -624,7 +646,8 @@ wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, cons
     if (((uintptr_t)rf & 15) || ((uintptr_t)out & 15))
         return fail(WF_ERR_UNSUPPORTED, "rf and out must be 16-byte aligned");
     const size_t esz = dtype == WF_RF_F32 ? 4 : 2;
-    if (n_rec > (1LL << 36) / n_s) return fail(WF_ERR_INVALID_ARG, "RF too large");
+    if (n_rec > (1LL << 36) / n_s || n_rec * ((n_s + 2047) / 2048) > 0x7FFFFFFFLL)
+        return fail(WF_ERR_INVALID_ARG, "RF too large");
     const long long total = (long long)n_rec * n_s;
     if (overlaps(rf, (size_t)total * esz, out, (size_t)total * 4))
         return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
@@ -632,7 +655,7 @@ wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, cons
     const int kp = n_taps <= 15 ? 15 : (n_taps <= 31 ? 31 : 63);
     const int pad = (kp - n_taps) / 2;
     for (int k = 0; k < n_taps; ++k) h.h[pad + k] = taps[k];
-    hipError_t e = wf::launch_fir(dtype, rf, total, n_s, kp, h, out, (hipStream_t)stream);
+    hipError_t e = wf::launch_fir(dtype, rf, (long long)n_rec, n_s, kp, h, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "FIR kernel launch");
     return ok();
 }

@@ -46,6 +46,25 @@ __device__ __forceinline__ uint32_t dist_q(ff dx, ff z2, int base) {
     return (uint32_t)h + (uint32_t)(int)rintf(corr * kQScale);
 }
 
+// Window-local distance, as dist_q, from a lateral offset dx = dxh + dxl
+// whose hi part lies on a grid 2^-g coarse enough that the channel and pixel
+// hi parts add exactly (host-chosen g), so forming dx costs two adds, and
+// with the base pre-scaled: bq = base * 2^23 (exact).  r^2 = dxh^2 + z2 is
+// formed with one TwoProd and one TwoSum (the dxl^2 term, < 2^-24, is
+// dropped); s - base is exact, so (s - base) 2^23 is one fused multiply-add.
+__device__ __forceinline__ uint32_t dist_q_grid(float dxh, float dxl, ff z2, float bq) {
+    const ff p = two_prod(dxh, dxh);
+    const float cross = (dxh + dxh) * dxl;
+    const ff r2 = two_sum(p.hi, z2.hi);
+    const float lo = r2.lo + (p.lo + (cross + z2.lo));
+    const float s = __builtin_amdgcn_sqrtf(r2.hi);
+    const ff sp = two_prod(s, s);
+    const float res = ((r2.hi - sp.hi) - sp.lo) + lo;  // r^2 - s^2
+    const float corr = res * ((0.5f * kQScale) * __builtin_amdgcn_rcpf(fmaxf(s, 1e-30f)));
+    const float h = fmaxf(fmaf(s, kQScale, -bq), 0.0f);
+    return (uint32_t)h + (uint32_t)(int)rintf(corr);
+}
+
 typedef float v2f __attribute__((ext_vector_type(2)));
 
 // Byte address of window entry (u >> 23) at byte offset `off`: one shift
@@ -224,7 +243,8 @@ __device__ __forceinline__ void tx_tables(const DasArgs& a, const TileGeom& g, i
 template <int PX>
 struct PixelSet {
     float qz[PX], qx[PX];   // tile-local indices (exact in float)
-    ff zp[PX], z2[PX], ixdx[PX];
+    ff zp[PX], z2[PX];
+    float xh[PX], xl[PX];   // lateral offset of the pixel from column 0, hi on the 2^-g grid
     bool valid[PX];
     int iz[PX], ix[PX];
 };
@@ -270,7 +290,9 @@ __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
         p.qx[k] = (float)qxi;
         p.zp[k] = ff_add(ff_make(a.Z0.x, a.Z0.y), ff_mul_f(ff_make(a.dZ.x, a.dZ.y), (float)iz));
         p.z2[k] = ff_sqr(p.zp[k]);
-        p.ixdx[k] = ff_mul_f(ff_make(a.dX.x, a.dX.y), (float)ix);
+        const ff ixdx = ff_mul_f(ff_make(a.dX.x, a.dX.y), (float)ix);
+        p.xh[k] = rintf(ixdx.hi * a.dxq) * a.inv_dxq;
+        p.xl[k] = (ixdx.hi - p.xh[k]) + ixdx.lo;
     }
 }
 
@@ -305,12 +327,14 @@ __device__ __forceinline__ void rx_delays(const DasArgs& a, const PixelSet<PX>& 
         const int c = c0 + j;
         if (c < a.C) {
             const ChConst cc = a.ch_tab[c];
+            const float bq = (float)bj[j] * kQScale;
 #pragma unroll
             for (int k = 0; k < PX; ++k) {
-                const ff d = ff_add(ff_make(cc.x, cc.y), p.ixdx[k]);
-                const bool on =
-                    p.valid[k] && !(a.fnum2 > 0.0f && a.fnum2 * fabsf(d.hi) > p.zp[k].hi);
-                const uint32_t q = min(dist_q(d, p.z2[k], bj[j]), a.rxspan_q);
+                const float dxh = cc.x + p.xh[k];  // exact: both on the 2^-g grid
+                const float dxl = cc.y + p.xl[k];
+                const bool on = p.valid[k] &&
+                                !(a.fnum2 > 0.0f && a.fnum2 * fabsf(dxh + dxl) > p.zp[k].hi);
+                const uint32_t q = min(dist_q_grid(dxh, dxl, p.z2[k], bq), a.rxspan_q);
                 rq[k][j] = on ? q : masked;
             }
         } else {
@@ -333,11 +357,18 @@ __device__ __forceinline__ void tx_delays(const DasArgs& a, const PixelSet<PX>& 
 #pragma unroll
         for (int k = 0; k < PX; ++k) tq[k] = min(q0 + (uint32_t)(k * dq), a.txspan_q);
     } else {
+        if (a.O.x == 0.0f && a.O.y == 0.0f) {  // t0 = 0: window-local distance
+            const float bq = (float)at * kQScale;
 #pragma unroll
-        for (int k = 0; k < PX; ++k) {
-            const ff d = ff_add(ff_make(q.x, q.y), p.ixdx[k]);
-            const ff v = ff_add(dist_ff(d, p.z2[k]), ff_make(a.O.x, a.O.y));
-            tq[k] = min(to_q(v, at), a.txspan_q);
+            for (int k = 0; k < PX; ++k)
+                tq[k] = min(dist_q_grid(q.x + p.xh[k], q.y + p.xl[k], p.z2[k], bq), a.txspan_q);
+        } else {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const ff d = ff_add(ff_make(q.x + p.xh[k], 0.0f), ff_make(q.y + p.xl[k], 0.0f));
+                const ff v = ff_add(dist_ff(d, p.z2[k]), ff_make(a.O.x, a.O.y));
+                tq[k] = min(to_q(v, at), a.txspan_q);
+            }
         }
     }
 }

@@ -1,22 +1,22 @@
-// FIR pre-filter along samples (K0) and windowed envelope moments (K6) for
+// FIR pre-filter along samples (K0) and windowed envelope moments (K7) for
 // gfx950.
 //
 // K0 (pre-processing FIR, Sec. II-B list of ops).  Every record of S samples
 // (one channel of one transmit of one frame) is filtered on its own:
 //   y[s] = sum_k h[k] r[s + D - k],  D = (K - 1) / 2,  r = 0 outside [0, S),
-// so an odd-length linear-phase filter adds no delay.  The records are
-// contiguous, so the whole RF array is one flat sequence: a workgroup
-// filters 2048 consecutive outputs, staging them plus a 32-sample halo on
-// each side in LDS as FP32 (int16 and FP16 convert exactly).  A lane owns 8
-// consecutive outputs - S % 8 == 0 keeps them inside one record - reads its
-// K + 7 inputs from LDS into registers with 16-byte reads, zeroes the ones
-// that fall in a neighbouring record (only lanes within D of a record edge
-// do this), and runs 8 K FMAs with the taps in scalar registers.  The tap
-// count is padded to KP in {15, 31, 63} with zeros placed symmetrically,
-// which adds exact zeros to the sums.  Per output: K FMAs, 2-4 bytes read
-// and 4 written; at K = 31 the vector-FMA and HBM times are about equal.
+// so an odd-length linear-phase filter adds no delay.  A workgroup filters
+// one segment of up to 2048 outputs of one record, staging the segment plus
+// a 32-sample halo on each side in LDS as FP32 (int16 and FP16 convert
+// exactly), with zeros wherever the halo leaves the record - so no lane ever
+// tests a record edge.  A lane owns 8 consecutive outputs (S % 8 == 0),
+// reads its K + 7 inputs from LDS into registers and runs 8 K FMAs with the
+// taps in scalar registers; lanes past the record's end exit (whole waves
+// when S < 2048).  The tap count is padded to KP in {15, 31, 63} with zeros
+// placed symmetrically, which adds exact zeros to the sums.  Per output: K
+// FMAs, 2-4 bytes read and 4 written; at K = 31 the vector-FMA and HBM
+// times are about equal.
 //
-// K6 (qUS moment maps, Fig. 3: slice -> E[X], E[X^2], E[X^3]).  Window
+// K7 (qUS moment maps, Fig. 3: slice -> E[X], E[X^2], E[X^3]).  Window
 // wz x wx at origins (i sz, j sx), whole windows only.  One workgroup per
 // (window row i, frame): the lanes first sum env, env^2, env^3 down the wz
 // rows of every needed column (reads coalesced along x), keep the column
@@ -72,7 +72,7 @@ __device__ __forceinline__ void load8<float>(const float* p, float (&v)[8]) {
 
 template <typename RT, int KP>
 __global__ void __launch_bounds__(kFirThreads)
-    fir_kernel(const RT* __restrict__ rf, float* __restrict__ out, long long total, int S,
+    fir_kernel(const RT* __restrict__ rf, float* __restrict__ out, int S, int nseg,
                const FirTaps taps) {
     constexpr int D = (KP - 1) / 2;
     constexpr int kStage = kFirBlock + 2 * kFirHalo;
@@ -85,13 +85,15 @@ __global__ void __launch_bounds__(kFirThreads)
     __shared__ __align__(16) float xs[kStage];
 
     const int tid = threadIdx.x;
-    const long long base = (long long)blockIdx.x * kFirBlock;
-    // ---- stage [base - halo, base + block + halo) as FP32, zeros outside ----
+    const long long rec = blockIdx.x / nseg;
+    const int sb = (int)(blockIdx.x - rec * nseg) * kFirBlock;  // first output
+    const RT* row = rf + rec * S;
+    // ---- stage [sb - halo, sb + block + halo) of the record, zeros outside --
     for (int c = tid; c < kStage / 8; c += kFirThreads) {
-        const long long q = base - kFirHalo + 8LL * c;  // multiple of 8
+        const int q = sb - kFirHalo + 8 * c;  // multiple of 8, as is S
         float v[8];
-        if (q >= 0 && q < total) {
-            load8<RT>(rf + q, v);
+        if (q >= 0 && q < S) {
+            load8<RT>(row + q, v);
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i) v[i] = 0.0f;
@@ -102,8 +104,8 @@ __global__ void __launch_bounds__(kFirThreads)
     }
     __syncthreads();
 
-    const long long p0 = base + (long long)kFirPerLane * tid;
-    if (p0 >= total) return;
+    const int s0 = sb + kFirPerLane * tid;
+    if (s0 >= S) return;
     float xw[kRead * 4];
     const float4* src = reinterpret_cast<const float4*>(xs + kFirPerLane * tid + kFirst);
 #pragma unroll
@@ -114,16 +116,7 @@ __global__ void __launch_bounds__(kFirThreads)
         xw[4 * r + 2] = q.z;
         xw[4 * r + 3] = q.w;
     }
-    // input m (record position s0 - D + m) sits at xw[kLead + m]; zero the
-    // ones outside this record
-    const int s0 = (int)(p0 % S);
-    if (s0 < D || s0 + kFirPerLane + D > S) {
-        const int lo = D - s0;      // m < lo: before the record
-        const int hi = S - s0 + D;  // m >= hi: after it
-#pragma unroll
-        for (int m = 0; m < kWin; ++m)
-            if (m < lo || m >= hi) xw[kLead + m] = 0.0f;
-    }
+    // input m (record position s0 - D + m) sits at xw[kLead + m]
     float acc[kFirPerLane];
 #pragma unroll
     for (int i = 0; i < kFirPerLane; ++i) acc[i] = 0.0f;
@@ -134,24 +127,24 @@ __global__ void __launch_bounds__(kFirThreads)
         for (int i = 0; i < kFirPerLane; ++i)
             acc[i] = fmaf(h, xw[kLead + i + KP - 1 - k], acc[i]);
     }
-    float4* dst = reinterpret_cast<float4*>(out + p0);
+    float4* dst = reinterpret_cast<float4*>(out + rec * S + s0);
     dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
     dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
 }
 
 template <typename RT>
-hipError_t launch_fir_t(const RT* rf, long long total, int S, int kp, const FirTaps& taps,
+hipError_t launch_fir_t(const RT* rf, long long n_rec, int S, int kp, const FirTaps& taps,
                         float* out, hipStream_t s) {
-    const long long blocks = (total + kFirBlock - 1) / kFirBlock;
-    const dim3 grid((unsigned)blocks);
+    const int nseg = (S + kFirBlock - 1) / kFirBlock;
+    const dim3 grid((unsigned)(n_rec * nseg));
     if (kp == 15)
-        hipLaunchKernelGGL((fir_kernel<RT, 15>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+        hipLaunchKernelGGL((fir_kernel<RT, 15>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
                            taps);
     else if (kp == 31)
-        hipLaunchKernelGGL((fir_kernel<RT, 31>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+        hipLaunchKernelGGL((fir_kernel<RT, 31>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
                            taps);
     else
-        hipLaunchKernelGGL((fir_kernel<RT, 63>), grid, dim3(kFirThreads), 0, s, rf, out, total, S,
+        hipLaunchKernelGGL((fir_kernel<RT, 63>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
                            taps);
     return hipGetLastError();
 }
@@ -202,12 +195,12 @@ __global__ void __launch_bounds__(kMomThreads)
 
 }  // namespace
 
-hipError_t launch_fir(int dtype, const void* rf, long long total, int S, int kp,
+hipError_t launch_fir(int dtype, const void* rf, long long n_rec, int S, int kp,
                       const FirTaps& taps, float* out, hipStream_t s) {
     switch (dtype) {
-        case 0: return launch_fir_t(static_cast<const int16_t*>(rf), total, S, kp, taps, out, s);
-        case 1: return launch_fir_t(static_cast<const __half*>(rf), total, S, kp, taps, out, s);
-        default: return launch_fir_t(static_cast<const float*>(rf), total, S, kp, taps, out, s);
+        case 0: return launch_fir_t(static_cast<const int16_t*>(rf), n_rec, S, kp, taps, out, s);
+        case 1: return launch_fir_t(static_cast<const __half*>(rf), n_rec, S, kp, taps, out, s);
+        default: return launch_fir_t(static_cast<const float*>(rf), n_rec, S, kp, taps, out, s);
     }
 }
 

@@ -34,7 +34,8 @@ struct TxConst {
     float4 v0, v1;
 };
 
-// Per-channel constants: (DX.hi, DX.lo, xe, 0), DX = X(column 0) - x_e.
+// Per-channel constants: (DX.hi, DX.lo, xe, 0), DX = X(column 0) - x_e, with
+// DX.hi on the 2^-g grid of DasArgs::dxq (so is the STAI transmit DX).
 typedef float4 ChConst;
 
 struct DasArgs {
@@ -55,6 +56,7 @@ struct DasArgs {
     float2 O;           // STAI: -t0 fs added to the transmit delay
     float fnum2;        // 2 F# (0: no apodisation)
     float x0f, dxf;     // lateral grid in samples (float) for window bases
+    float dxq, inv_dxq; // 2^g and 2^-g: grid of the hi parts of lateral offsets
     float t0fs;         // t0 * fs (d y / d c: time of flight = index + t0 fs)
     float neg_inv_c;    // -1 / c (d y / d c scale)
     const TxConst* tx_tab;
@@ -93,7 +95,7 @@ hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, f
                            hipStream_t s);
 hipError_t launch_log_compress(const float* env, const float* col_max, int F, int nz, int nx,
                                float dr_db, int offset, float* out, hipStream_t s);
-hipError_t launch_fir(int dtype, const void* rf, long long total, int S, int kp,
+hipError_t launch_fir(int dtype, const void* rf, long long n_rec, int S, int kp,
                       const FirTaps& taps, float* out, hipStream_t s);
 hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int wx, int sz,
                           int sx, int mz, int mx, float* out, hipStream_t s);

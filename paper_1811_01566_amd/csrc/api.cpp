@@ -306,7 +306,10 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
                 const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
                 const int span = (int)std::ceil(d) + 3;
                 const int nst = ((2 * span + 8) + 7) & ~7;
-                const int slot = nst + span + 8;
+                // windows of consecutive channels start 16 bytes apart
+                // modulo 128 (slot = 2 mod 16), so the 8 lanes that stage the
+                // same group of 8 consecutive channels store to distinct banks
+                const int slot = (((nst + span + 8) - 2 + 15) & ~15) + 2;
                 if (nst + span > 511) continue;
                 const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
                 if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
@@ -375,7 +378,6 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->ntx = tp->ntx;
     a->xcd_order = (WF_DAS_XCD_ORDER && (tp->ntz * tp->ntx) % 8 == 0) ? 1 : 0;
     a->ng = tp->nst / 8;
-    a->ng_inv = ((1 << 20) + a->ng - 1) / a->ng;
     a->nst = tp->nst;
     a->slot = tp->slot;
     a->txspan_q = (uint32_t)tp->span << wf::kQBits;

@@ -115,8 +115,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
                 if (w < ngroups) {
-                    const int j = (w * a.ng_inv) >> 20;
-                    const int gg = w - j * a.ng;
+                    const int j = w & (kChunk - 1);
+                    const int gg = w >> kChunkLog2;
                     const int c = c0 + j;
                     const int s0 = ((at + b_tab[j]) & ~7) + 8 * gg;
                     if (c < a.C && s0 >= 0 && s0 + 8 <= a.S)
@@ -133,8 +133,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
                 if (w < ngroups) {
-                    const int j = (w * a.ng_inv) >> 20;
-                    const int gg = w - j * a.ng;
+                    const int j = w & (kChunk - 1);
+                    const int gg = w >> kChunkLog2;
                     const int c = c0 + j;
                     const int s0 = ((at + b_tab[j]) & ~7) + 8 * gg;
                     float v[9];
@@ -172,14 +172,14 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         int t = next_active(0);
         if (t >= a.T) continue;  // no transmit reaches this tile through this chunk
 
-        uint32_t rq[PX][kChunk];
-        rx_delays<PX>(a, p, c0, bj, rq);
-
         // software pipeline over transmit passes, two LDS buffers: commit
         // pass t into buffer `cur` (last read two passes ago, before the
         // barrier of the previous iteration), barrier, then issue the loads
-        // of the next pass so that they fly while pass t is accumulated
+        // of the next pass so that they fly while pass t is accumulated.  The
+        // first pass's loads fly while the receive delays are formed.
         issue(t);
+        uint32_t rq[PX][kChunk];
+        rx_delays<PX>(a, p, c0, bj, rq);
         int cur = 0;
         while (t < a.T) {
             const int tn = next_active(t + 1);

@@ -11,7 +11,10 @@
 // tests a record edge.  A lane owns 8 consecutive outputs (S % 8 == 0),
 // reads its K + 7 inputs from LDS into registers and runs 8 K FMAs with the
 // taps in scalar registers; lanes past the record's end exit (whole waves
-// when S < 2048).  The tap count is padded to KP in {15, 31, 63} with zeros
+// when S < 2048).  The staged samples are stored with one pad word after
+// every 8, so lane i's window starts at word 9 i: 9 is odd, so neighbouring
+// lanes hit different LDS banks (a stride of 8 words would put every 4th
+// lane on the same bank).  The tap count is padded to KP in {15, 31, 63} with zeros
 // placed symmetrically, which adds exact zeros to the sums.  Per output: K
 // FMAs, 2-4 bytes read and 4 written; at K = 31 the vector-FMA and HBM
 // times are about equal.
@@ -75,14 +78,11 @@ __global__ void __launch_bounds__(kFirThreads)
     fir_kernel(const RT* __restrict__ rf, float* __restrict__ out, int S, int nseg,
                const FirTaps taps) {
     constexpr int D = (KP - 1) / 2;
-    constexpr int kStage = kFirBlock + 2 * kFirHalo;
-    // the lane's inputs start at LDS entry 8 lane + kFirHalo - D; read the
-    // 16-byte-aligned superset
-    constexpr int kLead = (kFirHalo - D) & 3;
-    constexpr int kFirst = (kFirHalo - D) - kLead;
+    constexpr int kStage = kFirBlock + 2 * kFirHalo;       // staged samples
+    constexpr int kFirst = kFirHalo - D;                   // lane's first sample - 8 lane
     constexpr int kWin = KP + kFirPerLane - 1;             // inputs a lane needs
-    constexpr int kRead = (kLead + kWin + 3) / 4;          // float4 reads
-    __shared__ __align__(16) float xs[kStage];
+    // sample e of the staged range lives at word e + e / 8
+    __shared__ float xs[kStage + kStage / 8];
 
     const int tid = threadIdx.x;
     const long long rec = blockIdx.x / nseg;
@@ -98,25 +98,21 @@ __global__ void __launch_bounds__(kFirThreads)
 #pragma unroll
             for (int i = 0; i < 8; ++i) v[i] = 0.0f;
         }
-        float4* d = reinterpret_cast<float4*>(xs + 8 * c);
-        d[0] = make_float4(v[0], v[1], v[2], v[3]);
-        d[1] = make_float4(v[4], v[5], v[6], v[7]);
+        float* d = xs + 9 * c;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d[i] = v[i];
     }
     __syncthreads();
 
     const int s0 = sb + kFirPerLane * tid;
     if (s0 >= S) return;
-    float xw[kRead * 4];
-    const float4* src = reinterpret_cast<const float4*>(xs + kFirPerLane * tid + kFirst);
+    // input m (record position s0 - D + m) is staged sample e = 8 lane +
+    // kFirst + m, at word e + e / 8 = 9 lane + (kFirst + m) + (kFirst + m) / 8
+    constexpr int kLead = 0;
+    float xw[kWin];
+    const float* src = xs + 9 * tid;
 #pragma unroll
-    for (int r = 0; r < kRead; ++r) {
-        const float4 q = src[r];
-        xw[4 * r] = q.x;
-        xw[4 * r + 1] = q.y;
-        xw[4 * r + 2] = q.z;
-        xw[4 * r + 3] = q.w;
-    }
-    // input m (record position s0 - D + m) sits at xw[kLead + m]
+    for (int m = 0; m < kWin; ++m) xw[m] = src[(kFirst + m) + (kFirst + m) / 8];
     float acc[kFirPerLane];
 #pragma unroll
     for (int i = 0; i < kFirPerLane; ++i) acc[i] = 0.0f;

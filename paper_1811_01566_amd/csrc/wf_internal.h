@@ -11,6 +11,7 @@ namespace wf {
 // Channels staged per pass of the DAS kernel: their one-way receive delays
 // stay in registers while every transmit streams through LDS.
 constexpr int kChunk = 16;
+constexpr int kChunkLog2 = 4;
 // Threads per DAS workgroup (4 wave64 waves); launch plans may also use
 // 512-thread workgroups with 2 pixels per thread.
 constexpr int kThreads = 256;
@@ -46,9 +47,8 @@ struct DasArgs {
     int ntz, ntx;       // tiles along z and x
     int xcd_order;      // 1: tile order grouped per XCD (tile count % 8 == 0)
     int ng;             // 8-sample groups staged per window (nst / 8)
-    int ng_inv;         // ceil(2^20 / ng), exact division for small numerators
     int nst;            // staged entries per window
-    int slot;           // LDS entries per window (staged + zero pad)
+    int slot;           // LDS entries per window (staged + zero pad), = 2 mod 16
     uint32_t txspan_q;  // clamp of window-local transmit delays (Q9.23)
     uint32_t rxspan_q;  // clamp of window-local receive delays (Q9.23)
     float2 Z0, dZ;      // depth of row 0 and row step, samples (float-float)

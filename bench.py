@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--workload", default="pwi", choices=["pwi", "stai_full", "stai_small",
                                                           "pwi_batch8", "paper_stai",
                                                           "paper_pwi"])
+    ap.add_argument("--rf-dtype", default="int16", choices=["int16", "float16", "float32"],
+                    help="RF storage: int16 ADC counts, FP16 (counts x 2^-13) or FP32")
     ap.add_argument("--latency-frames", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=256,
@@ -291,6 +293,10 @@ def main():
 
     scan = scan_of(wf, w)
     rf = torch.from_numpy(rf_np).to(dev)
+    if args.rf_dtype == "float16":
+        rf = (rf.float() * 2.0 ** -13).half()
+    elif args.rf_dtype == "float32":
+        rf = rf.float()
     F = w.n_frames
     y = torch.empty((F, w.nz, w.nx), dtype=torch.float32, device=dev)
     out = torch.empty_like(y)
@@ -368,6 +374,31 @@ def main():
     }
     del rf_f
 
+    # ---- derivatives: adjoint (d L / d rf) and forward-mode d y / d c -------
+    gcot = torch.randn(y.shape, generator=torch.Generator(device=dev).manual_seed(3),
+                       device=dev)
+    grad_rf = torch.empty(rf.shape, dtype=torch.float32, device=dev)
+    dydc = torch.empty_like(y)
+    adj_ms, dydc_ms = [], []
+    for i in range(8):
+        e0.record(stream)
+        wf.das_adjoint(scan, gcot, w.n_s, out=grad_rf)
+        e1.record(stream)
+        wf.das_dydc(scan, rf, out=dydc)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if i >= 2:
+            adj_ms.append(e0.elapsed_time(e1))
+            dydc_ms.append(e1.elapsed_time(e2))
+    derivatives = {
+        "adjoint_ms": round(float(np.mean(adj_ms)), 4),
+        "adjoint_note": "zero fill of the float32 RF gradient + LDS-atomic scatter kernel",
+        "dydc_ms": round(float(np.mean(dydc_ms)), 4),
+        "adjoint_gcontrib_per_s": round(w.nominal_contributions / (np.mean(adj_ms) * 1e-3)
+                                        / 1e9, 1),
+    }
+    del grad_rf
+
     # ---- closed-loop frame latency: enqueue -> completion, one in flight --
     lat = []
     for _ in range(args.latency_frames):
@@ -398,7 +429,7 @@ def main():
         "config": {
             "workload": w.name,
             "mode": w.mode, "frames_per_step": F, "n_tx": w.n_tx, "n_ch": w.n_ch,
-            "n_s": w.n_s, "grid": [w.nz, w.nx], "rf_dtype": "int16",
+            "n_s": w.n_s, "grid": [w.nz, w.nx], "rf_dtype": args.rf_dtype,
             "depth_mm": [w.z_min * 1e3, w.z_max * 1e3], "f_number": w.f_number,
             "dr_db": w.dr_db,
         },
@@ -425,6 +456,7 @@ def main():
             "avg_launch_ms": round(das_avg_s * 1e3, 4),
         },
         "prefilter_and_qus": prefilter,
+        "derivatives": derivatives,
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:

@@ -58,13 +58,14 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 1
+#define WF_ABI_VERSION 2
 
 typedef enum {
     WF_OK = 0,
     WF_ERR_INVALID_ARG = -1, /* a null pointer, a size or value out of range */
     WF_ERR_UNSUPPORTED = -2, /* valid, but outside what the kernels handle  */
-    WF_ERR_DEVICE = -3       /* a HIP runtime call failed                   */
+    WF_ERR_DEVICE = -3,      /* a HIP runtime call failed                   */
+    WF_ERR_WORKSPACE = -4    /* the caller's workspace is too small          */
 } wf_status;
 
 typedef enum {
@@ -195,15 +196,31 @@ wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const
 /*
  * Adjoint of DAS w.r.t. the RF (the transpose of the interpolating gather):
  * for a cotangent g, grad_rf[t][j][m] = sum_p w_j(p) g(p) ((1-a)[m = n] +
- * a [m = n+1]) over pairs with 0 <= n <= S-2.  grad_rf is overwritten.
- *   g        DEVICE float [F][nz][nx].
- *   grad_rf  DEVICE float [F][T][C][S]; acq->dtype must be WF_RF_F32.
- * Accumulated with float atomics: reproducible to FP32 rounding, not bitwise.
+ * a [m = n+1]) over pairs with 0 <= n <= S-2.  The beamformer sits in a
+ * trainable graph in the paper (Sec. I; Sec. IV); this is the gradient that
+ * flows back to the RF.  grad_rf is overwritten (every sample written once).
+ *   g          DEVICE float [F][nz][nx].
+ *   grad_rf    DEVICE float [F][T][C][S]; acq->dtype must be WF_RF_F32.
+ *   workspace  DEVICE, 256-byte aligned, >= the bytes wf_das_adjoint_workspace
+ *              reports (it holds one frame's per-tile windows; frames run one
+ *              after another on `stream`); caller-owned, contents ignored.
+ * Per-tile windows are accumulated with LDS float atomics and then summed in
+ * a fixed tile order without global atomics: reproducible to FP32 rounding,
+ * not bitwise.  Returns WF_ERR_WORKSPACE if the workspace is too small.
  * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
  */
 wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                          const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                         const wf_grid* grid, const float* g, float* grad_rf, void* stream);
+                         const wf_grid* grid, const float* g, float* grad_rf, void* workspace,
+                         uint64_t workspace_bytes, void* stream);
+
+/*
+ * Device bytes of the workspace wf_das_adjoint needs for this geometry (one
+ * frame; acq->n_frames is ignored).  Host only.
+ */
+wf_status wf_das_adjoint_workspace(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                                   const int32_t* tx_elem, const double* angles_rad,
+                                   int32_t tref, const wf_grid* grid, uint64_t* bytes);
 
 /*
  * out[0] = sum_i a[i] b[i] (DEVICE pointers, n elements; compensated sums in

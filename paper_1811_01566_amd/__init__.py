@@ -26,6 +26,7 @@ from ._lib import WfError, load
 
 __all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
            "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info",
+           "adjoint_workspace_bytes",
            "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd"]
 
 
@@ -352,20 +353,39 @@ def das_dydc(scan: Scan, rf, out=None, stream=None):
     return out
 
 
-def das_adjoint(scan: Scan, g, n_s: int, out=None, stream=None):
+def adjoint_workspace_bytes(scan: Scan, n_s: int) -> int:
+    """Device bytes of the workspace one :func:`das_adjoint` call needs."""
+    lib = load()
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, 1, n_s, _lib.WF_RF_F32)
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    n = ctypes.c_uint64(0)
+    _lib.check(lib.wf_das_adjoint_workspace(mode, probe, acq, tx, ang, tref, grid,
+                                            ctypes.byref(n)), "wf_das_adjoint_workspace")
+    return int(n.value)
+
+
+def das_adjoint(scan: Scan, g, n_s: int, out=None, workspace=None, stream=None):
     """Adjoint of DAS: cotangent g [F][nz][nx] -> d L / d rf [F][T][C][S]
-    (float32; accumulated with atomics, reproducible to FP32 rounding)."""
+    (float32; per-tile windows summed in tile order without global atomics,
+    reproducible to FP32 rounding).  `workspace` (a uint8 device tensor of at
+    least :func:`adjoint_workspace_bytes`) is allocated when not given."""
     torch = _torch()
     lib = load()
     g3 = g.unsqueeze(0) if g.dim() == 2 else g
     nf = g3.shape[0]
     if out is None:
         out = torch.empty((nf, scan.n_tx, scan.n_ch, n_s), dtype=torch.float32, device=g.device)
+    if workspace is None:
+        workspace = torch.empty(adjoint_workspace_bytes(scan, n_s), dtype=torch.uint8,
+                                device=g.device)
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, n_s, _lib.WF_RF_F32)
     mode, tx, ang, tref = _mode_args(scan, keep)
     _lib.check(lib.wf_das_adjoint(mode, probe, acq, tx, ang, tref, grid, _dev(g3, "g"),
-                                  _dev(out, "grad_rf"), _stream_ptr(g3, stream)),
+                                  _dev(out, "grad_rf"), _dev(workspace, "workspace"),
+                                  ctypes.c_uint64(workspace.numel() * workspace.element_size()),
+                                  _stream_ptr(g3, stream)),
                "wf_das_adjoint")
     return out
 

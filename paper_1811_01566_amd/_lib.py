@@ -12,6 +12,8 @@ WF_OK = 0
 WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
+WF_ERR_WORKSPACE = -4
+WF_ABI_VERSION = 2
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2
 WF_PWI_TREF_FIRST, WF_PWI_TREF_CENTRE = 0, 1
@@ -53,7 +55,9 @@ SIGNATURES = {
                              c_int32_p]),
     "wf_das_dydc": (I, [I, V, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V]),
     "wf_das_adjoint": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
-                           V]),
+                           V, ctypes.c_uint64, V]),
+    "wf_das_adjoint_workspace": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I,
+                                     P(WfGrid), ctypes.POINTER(ctypes.c_uint64)]),
     "wf_dot": (I, [V, V, ctypes.c_int64, V, V]),
     "wf_envelope": (I, [V, I, I, I, V, V, V]),
     "wf_log_compress": (I, [V, V, I, I, I, F, I, V, V]),

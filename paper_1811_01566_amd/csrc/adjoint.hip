@@ -6,13 +6,21 @@
 // scatters a cotangent g(p) back to the samples: (1 - a) w g to r[n] and
 // a w g to r[n+1], for pairs with 0 <= n <= S-2.
 //
-// K5 reuses the forward's tiles, window bases and window-local Q9.23 delays
-// (das_common.h), so a contribution lands in exactly the pair the forward
-// read.  Per transmit pass it accumulates, for every window entry (= pair n),
-// G[n] = sum w g and H[n] = sum a w g with LDS float atomics; then sample s
-// receives (G[s] - H[s]) + H[s-1] (each only for valid pairs) through one
-// global float atomic per touched sample.  The order of the global atomics is
-// not fixed, so the gradient is reproducible only to FP32 rounding.
+// Two stages, no global atomics:
+//  1. K5 reuses the forward's tiles, window bases and window-local Q9.23
+//     delays (das_common.h), so a contribution lands in exactly the pair the
+//     forward read.  Per transmit pass it accumulates, for every window entry
+//     (= pair n), G[n] = sum w g and H[n] = sum a w g with LDS float atomics;
+//     sample A0 + e of the window then receives (G[e] - H[e]) + H[e-1] (each
+//     only for valid pairs).  The window of every (transmit, channel, tile)
+//     goes to a workspace with its first sample A0 (or a no-window mark when
+//     the pass or the channel chunk reaches nothing).
+//  2. K5r sums, for every RF sample, the windows of all tiles that cover it,
+//     in tile order: one lane per sample, with a scalar test that skips the
+//     tiles whose window misses the workgroup's 256 samples.  Every sample of
+//     the gradient is written exactly once.
+// The LDS atomics of stage 1 add in no fixed order, so the gradient is
+// reproducible to FP32 rounding, not bitwise.
 #pragma clang fp contract(off)
 
 #include "das_common.h"
@@ -34,6 +42,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
     const int frame = blockIdx.y;
+    const int tile = blockIdx.x;
     const TileGeom g = tile_geom<NT, PX>(a, blockIdx.x);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
     for (int i = tid; i < kChunk * slot; i += NT) win[i] = make_float2(0.0f, 0.0f);
@@ -44,8 +53,9 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
 #pragma unroll
     for (int k = 0; k < PX; ++k)
         gp[k] = p.valid[k] ? a.g[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] : 0.0f;
-    float* grad_frame = a.grad + (size_t)frame * a.T * a.C * a.S;
     const int ne = a.nst + 1;  // samples a window can touch
+    // workspace slots of (transmit t, channel c) for this tile
+    auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };
 
     for (int c0 = 0; c0 < a.C; c0 += kChunk) {
         __syncthreads();
@@ -60,14 +70,23 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             bmin = min(bmin, bj[j]);
             bmax = max(bmax, bj[j]);
         }
-        if (!any_act) continue;
+        if (!any_act) {  // nothing of this chunk reaches the tile
+            for (int w = tid; w < a.T * kChunk; w += NT) {
+                const int t = w >> kChunkLog2, c = c0 + (w & (kChunk - 1));
+                if (c < a.C) a.ws_a0[slot_of(t, c)] = kNoWindow;
+            }
+            continue;
+        }
 
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
 
         for (int t = 0; t < a.T; ++t) {
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
-            if (at + bmin > a.S - 2 || at + bmax + a.nst < 0) continue;  // nothing lands
+            if (at + bmin > a.S - 2 || at + bmax + a.nst < 0) {  // nothing lands
+                if (tid < kChunk && c0 + tid < a.C) a.ws_a0[slot_of(t, c0 + tid)] = kNoWindow;
+                continue;
+            }
             uint32_t tq[PX];
             tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
 
@@ -87,19 +106,21 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             }
             __syncthreads();
 
-            // ---- flush: sample s = A0 + e of every window ------------------
+            // ---- flush: sample A0 + e of every window to the workspace ------
             for (int w = tid; w < kChunk * ne; w += NT) {
                 const int j = w / ne;
                 const int e = w - j * ne;
                 const int c = c0 + j;
+                if (c >= a.C) continue;
                 const int A0 = (at + b_tab[j]) & ~7;
                 const int s = A0 + e;
                 const float2* wj = win + j * slot;
                 float v = 0.0f;
                 if (e < a.nst && s >= 0 && s <= a.S - 2) v += wj[e].x - wj[e].y;
                 if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += wj[e - 1].y;
-                if (c < a.C && v != 0.0f && s >= 0 && s < a.S)
-                    unsafeAtomicAdd(grad_frame + ((size_t)t * a.C + c) * a.S + s, v);
+                const size_t sl = slot_of(t, c);
+                a.ws_win[sl * ne + e] = v;
+                if (e == 0) a.ws_a0[sl] = A0;
             }
             __syncthreads();
             for (int w = tid; w < kChunk * a.nst; w += NT) {
@@ -109,6 +130,29 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             __syncthreads();  // windows are zero before the next pass scatters
         }
     }
+}
+
+// Stage 2: lane = RF sample s of row (t, c); the sum over tiles in tile
+// order of the window entries that land on s.
+constexpr int kRedThreads = 256;
+
+__global__ void __launch_bounds__(kRedThreads)
+    adjoint_reduce_kernel(const float* __restrict__ ws_win, const int* __restrict__ ws_a0,
+                          float* __restrict__ grad, int ntiles, int ne, int S) {
+    const size_t row = blockIdx.x;
+    const int s_lo = blockIdx.y * kRedThreads;
+    const int s = s_lo + (int)threadIdx.x;
+    const int* a0r = ws_a0 + row * ntiles;
+    const float* wr = ws_win + row * ntiles * (size_t)ne;
+    float acc = 0.0f;
+    for (int k = 0; k < ntiles; ++k) {
+        const int A0 = __builtin_amdgcn_readfirstlane(a0r[k]);
+        // scalar test: does the window [A0, A0 + ne) meet [s_lo, s_lo + 256)?
+        if (A0 == kNoWindow || A0 + ne <= s_lo || A0 >= s_lo + kRedThreads) continue;
+        const int e = s - A0;
+        if (e >= 0 && e < ne) acc += wr[(size_t)k * ne + e];
+    }
+    if (s < S) grad[row * S + s] = acc;
 }
 
 __global__ void __launch_bounds__(256) fill_kernel(float* p, size_t n, float v) {
@@ -169,6 +213,14 @@ hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t
                               hipStream_t s) {
     return mode == 1 ? launch_adj_shape<1>(nt, px, a, lds_bytes, s)
                      : launch_adj_shape<0>(nt, px, a, lds_bytes, s);
+}
+
+hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,
+                                 int ntiles, int ne, int S, hipStream_t s) {
+    const dim3 grid((unsigned)rows, (unsigned)((S + kRedThreads - 1) / kRedThreads));
+    hipLaunchKernelGGL(adjoint_reduce_kernel, grid, dim3(kRedThreads), 0, s, ws_win, ws_a0, grad,
+                       ntiles, ne, S);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s) {

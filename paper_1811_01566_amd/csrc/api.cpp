@@ -477,9 +477,35 @@ wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const
                       mode == 1 ? angles_rad : nullptr, tref, grid, dydc, stream);
 }
 
+// Workspace of the two-stage adjoint for one frame: every (transmit,
+// channel, tile) window (nst + 1 floats) and its first sample (int).
+size_t adjoint_ws_bytes(const wf_acq* acq, const TilePlan& tp) {
+    const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
+    return slots * (size_t)(tp.nst + 1) * 4 + slots * 4 + 256;
+}
+
+wf_status wf_das_adjoint_workspace(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                                   const int32_t* tx_elem, const double* angles_rad,
+                                   int32_t tref, const wf_grid* grid, uint64_t* bytes) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
+    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    if (st != WF_OK) return st;
+    Geometry g;
+    build_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                   mode == 1 ? angles_rad : nullptr, tref, grid, &g);
+    TilePlan tp;
+    if (!choose_tile(g, acq, grid, &tp))
+        return fail(WF_ERR_UNSUPPORTED, "pixel spacing too coarse for the DAS tile window");
+    *bytes = adjoint_ws_bytes(acq, tp);
+    return ok();
+}
+
 wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                          const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                         const wf_grid* grid, const float* g, float* grad_rf, void* stream) {
+                         const wf_grid* grid, const float* g, float* grad_rf, void* workspace,
+                         uint64_t workspace_bytes, void* stream) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
     wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
                                   mode == 1 ? angles_rad : nullptr, tref, grid, true);
@@ -488,8 +514,11 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
         return fail(WF_ERR_INVALID_ARG, "the RF gradient is float32 (acq->dtype=%d)", acq->dtype);
     if (!g) return fail(WF_ERR_INVALID_ARG, "g is NULL");
     if (!grad_rf) return fail(WF_ERR_INVALID_ARG, "grad_rf is NULL");
-    if (((uintptr_t)grad_rf & 3) != 0 || ((uintptr_t)g & 3) != 0)
-        return fail(WF_ERR_INVALID_ARG, "g and grad_rf must be 4-byte aligned");
+    if (!workspace) return fail(WF_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)grad_rf & 3) != 0 || ((uintptr_t)g & 3) != 0 ||
+        ((uintptr_t)workspace & 255) != 0)
+        return fail(WF_ERR_INVALID_ARG,
+                    "g and grad_rf must be 4-byte and workspace 256-byte aligned");
     const size_t gbytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
     if (overlaps(g, gbytes, grad_rf, rf_bytes_of(acq)))
         return fail(WF_ERR_INVALID_ARG, "grad_rf overlaps g");
@@ -498,13 +527,28 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     if ((st = prepare_das(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
                           mode == 1 ? angles_rad : nullptr, tref, grid, &a, &tp)) != WF_OK)
         return st;
-    a.g = g;
-    a.grad = grad_rf;
+    const size_t need = adjoint_ws_bytes(acq, tp);
+    if (workspace_bytes < need)
+        return fail(WF_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
+                    (unsigned long long)workspace_bytes, (unsigned long long)need);
+    if (overlaps(workspace, need, grad_rf, rf_bytes_of(acq)) || overlaps(workspace, need, g, gbytes))
+        return fail(WF_ERR_INVALID_ARG, "workspace overlaps g or grad_rf");
+    const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
+    a.ntiles = tp.ntz * tp.ntx;
+    a.ws_win = static_cast<float*>(workspace);
+    a.ws_a0 = reinterpret_cast<int*>(static_cast<char*>(workspace) + slots * (tp.nst + 1) * 4);
+    a.F = 1;  // one frame per launch pair: the workspace holds one frame
     const size_t lds = tp.lds - (size_t)wf::kChunk * tp.slot * 8;  // one window buffer
-    hipError_t e = wf::launch_fill(grad_rf, rf_bytes_of(acq) / 4, 0.0f, (hipStream_t)stream);
-    if (e == hipSuccess)
-        e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
+    for (int f = 0; f < acq->n_frames; ++f) {
+        a.g = g + (size_t)f * grid->nz * grid->nx;
+        hipError_t e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = wf::launch_adjoint_reduce(a.ws_win, a.ws_a0, grad_rf + (size_t)f * frame_rf,
+                                          acq->n_tx * acq->n_ch, a.ntiles, tp.nst + 1, acq->n_s,
+                                          (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    }
     return ok();
 }
 

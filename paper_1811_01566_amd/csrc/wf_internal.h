@@ -23,6 +23,8 @@ constexpr int kMaxGroups = 4;
 // fraction lines up with the float mantissa, the integer part (< 512)
 // indexes the LDS window.
 constexpr int kQBits = 23;
+// Adjoint workspace mark: the (transmit, channel, tile) window adds nothing.
+constexpr int kNoWindow = -0x40000000;
 
 // Per-transmit constants of a geometry, in samples (distances scaled by
 // fs / c), split into float-float pairs on the host from double.
@@ -63,6 +65,9 @@ struct DasArgs {
     const ChConst* ch_tab;
     const float* g;     // adjoint: cotangent [F][nz][nx]
     float* grad;        // adjoint: d L / d rf [F][T][C][S]
+    int ntiles;         // adjoint: ntz * ntx
+    float* ws_win;      // adjoint workspace: window of (t, c, tile), nst + 1 samples
+    int* ws_a0;         // adjoint workspace: first sample of that window or kNoWindow
 };
 
 struct DelayArgs {
@@ -88,6 +93,8 @@ hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, cons
                            size_t lds_bytes, hipStream_t s);
 hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
                               hipStream_t s);
+hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,
+                                 int ntiles, int ne, int S, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);

@@ -143,3 +143,26 @@ def test_autograd_function(wf_gpu):
     torch.cuda.synchronize()
     assert nl2(rf.grad.cpu().numpy(), gr.cpu().numpy()) <= 1e-6
     assert abs(float(c.grad) - float(dl)) <= 1e-6 * abs(float(dl))
+
+
+def test_adjoint_workspace_and_frames(wf_gpu):
+    """A short workspace is refused with WF_ERR_WORKSPACE; a two-frame call
+    equals the two one-frame calls (the workspace is reused frame by frame)."""
+    torch = _torch()
+    w = CASES["pwi_sub"]()
+    scan = scan_from_workload(w)
+    need = wf_gpu.adjoint_workspace_bytes(scan, w.n_s)
+    assert need > 0
+    rng = np.random.default_rng(12)
+    g = torch.from_numpy(rng.normal(size=(2, w.nz, w.nx)).astype(np.float32)).cuda()
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(wf_gpu.WfError) as ei:
+        wf_gpu.das_adjoint(scan, g, w.n_s, workspace=small)
+    assert ei.value.status == -4
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    both = wf_gpu.das_adjoint(scan, g, w.n_s, workspace=ws)
+    f0 = wf_gpu.das_adjoint(scan, g[0], w.n_s, workspace=ws)
+    f1 = wf_gpu.das_adjoint(scan, g[1], w.n_s, workspace=ws)
+    torch.cuda.synchronize()
+    for a, b in ((both[0], f0[0]), (both[1], f1[0])):
+        assert nl2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6

@@ -148,7 +148,7 @@ def test_autograd_function(wf_gpu):
 def test_adjoint_workspace_and_frames(wf_gpu):
     """A short workspace is refused with WF_ERR_WORKSPACE; a two-frame call
     equals the two one-frame calls (the workspace is reused frame by frame)."""
-    torch = _torch()
+    torch = _t()
     w = CASES["pwi_sub"]()
     scan = scan_from_workload(w)
     need = wf_gpu.adjoint_workspace_bytes(scan, w.n_s)

@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     for (int i = tid; i < kChunk * slot; i += NT) win[i] = make_float2(0.0f, 0.0f);
 
     PixelSet<PX> p;
-    pixel_set<NT, PX>(a, g, p);
+    pixel_set<NT, PX, false>(a, g, p);
     float gp[PX];
 #pragma unroll
     for (int k = 0; k < PX; ++k)

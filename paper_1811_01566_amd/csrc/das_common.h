@@ -261,7 +261,11 @@ struct PixelSet {
 #define WF_DAS_PATCH_LANES 1
 #endif
 
-template <int NT, int PX>
+// The adjoint scatters with LDS atomics and passes PATCH = false: down one
+// column the window entries rise with depth (both times of flight grow with
+// z), so the lanes of a wave mostly hit distinct addresses, where a 4 x 4
+// patch would pile several lanes onto each entry.
+template <int NT, int PX, bool PATCH = (WF_DAS_PATCH_LANES != 0)>
 __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
                                           PixelSet<PX>& p) {
     const int TZ = 1 << a.tz_log2;
@@ -269,7 +273,7 @@ __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
     for (int k = 0; k < PX; ++k) {
         const int q = k * NT + (int)threadIdx.x;
         int qzi, qxi;
-        if (WF_DAS_PATCH_LANES) {
+        if (PATCH) {
             const int l = q & 63, w = q >> 6;
             const int wz_log2 = a.tz_log2 >= 4 ? 4 : 3;  // wave slot 16 x 4 or 8 x 8
             const int lz = wz_log2 == 4 ? ((l & 3) | ((l >> 4) << 2))

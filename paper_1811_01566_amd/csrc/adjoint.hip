@@ -7,20 +7,28 @@
 // a w g to r[n+1], for pairs with 0 <= n <= S-2.
 //
 // Two stages, no global atomics:
+//  0. K5m: the largest |g| of the frame (one workgroup, fixed order).
 //  1. K5 reuses the forward's tiles, window bases and window-local Q9.23
 //     delays (das_common.h), so a contribution lands in exactly the pair the
 //     forward read.  Per transmit pass it accumulates, for every window entry
-//     (= pair n), G[n] = sum w g and H[n] = sum a w g with LDS float atomics;
-//     sample A0 + e of the window then receives (G[e] - H[e]) + H[e-1] (each
-//     only for valid pairs).  The window of every (transmit, channel, tile)
-//     goes to a workspace with its first sample A0 (or a no-window mark when
-//     the pass or the channel chunk reaches nothing).
+//     (= pair n), G[n] = sum w g and H[n] = sum a w g in 64-bit fixed point
+//     with LDS integer atomics: g is rounded once per pixel to 24 bits of the
+//     frame's largest |g| (g24), G adds g24 2^23 and H adds g24 times the
+//     23-bit fraction of the delay - the very fraction the forward
+//     interpolates with - as one 24 x 24-bit product.  (On gfx950 an LDS
+//     float atomic costs about 40 times an LDS 64-bit integer atomic.)
+//     Sample A0 + e of the window then receives (G[e] - H[e]) + H[e-1] (each
+//     only for valid pairs), converted back to float.  The window of every
+//     (transmit, channel, tile) goes to a workspace with its first sample A0
+//     (or a no-window mark when the pass or the channel chunk reaches
+//     nothing).
 //  2. K5r sums, for every RF sample, the windows of all tiles that cover it,
 //     in tile order: one lane per sample, with a scalar test that skips the
 //     tiles whose window misses the workgroup's 256 samples.  Every sample of
 //     the gradient is written exactly once.
-// The LDS atomics of stage 1 add in no fixed order, so the gradient is
-// reproducible to FP32 rounding, not bitwise.
+// Integer sums do not depend on their order and stage 2 has a fixed order,
+// so the gradient is bitwise reproducible.  Rounding g to 24 bits of the
+// frame maximum adds at most 2^-24 max|g| per pixel.
 #pragma clang fp contract(off)
 
 #include "das_common.h"
@@ -28,13 +36,26 @@
 namespace wf {
 namespace {
 
+// Window entry of the adjoint: 64-bit fixed-point G and H (scale 2^23 g24).
+struct AdjEntry {
+    unsigned long long g, h;
+};
+
+// Byte address of 16-byte window entry (u >> 23) at byte offset `off`.
+__device__ __forceinline__ uint32_t entry_addr16(uint32_t u, uint32_t off) {
+    const uint32_t idx = u >> kQBits;
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(idx), "s"(off));
+    return r;
+}
+
 template <int MODE, int NT, int PX>
 __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
-    const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
-    float2* win = reinterpret_cast<float2*>(smem);  // (G, H) per entry
+    const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(AdjEntry);
+    AdjEntry* win = reinterpret_cast<AdjEntry*>(smem);
     int4* m_tab = reinterpret_cast<int4*>(smem + buf_bytes);
     float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
     int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
@@ -45,14 +66,23 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     const int tile = blockIdx.x;
     const TileGeom g = tile_geom<NT, PX>(a, blockIdx.x);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
-    for (int i = tid; i < kChunk * slot; i += NT) win[i] = make_float2(0.0f, 0.0f);
+    for (int i = tid; i < kChunk * slot; i += NT) win[i] = AdjEntry{0ull, 0ull};
 
     PixelSet<PX> p;
     pixel_set<NT, PX, false>(a, g, p);
-    float gp[PX];
+    // g rounded to 24 bits of the frame maximum: |g24| <= 2^23
+    const float gmax = a.ws_gmax[frame];
+    const float to24 = gmax > 0.0f ? 8388608.0f / gmax : 0.0f;
+    int g24[PX];
+    unsigned long long gG[PX];  // G increment: g24 * 2^23
 #pragma unroll
-    for (int k = 0; k < PX; ++k)
-        gp[k] = p.valid[k] ? a.g[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] : 0.0f;
+    for (int k = 0; k < PX; ++k) {
+        const float gv = p.valid[k] ? a.g[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] : 0.0f;
+        g24[k] = ((int)rintf(gv * to24) << 8) >> 8;  // |value| <= 2^23: the shift keeps it
+        gG[k] = (unsigned long long)((long long)g24[k] << kQBits);
+    }
+    // fixed point -> float: 2^-23 (fraction) * gmax / 2^23 (g24)
+    const double unscale = (double)gmax * (1.0 / 70368744177664.0);  // 2^-46
     const int ne = a.nst + 1;  // samples a window can touch
     // workspace slots of (transmit t, channel c) for this tile
     auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };
@@ -90,18 +120,21 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             uint32_t tq[PX];
             tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
 
-            // ---- scatter into the LDS windows ------------------------------
+            // ---- scatter into the LDS windows (integer atomics) -------------
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 16u;
 #pragma unroll
                 for (int k = 0; k < PX; ++k) {
-                    if (gp[k] == 0.0f) continue;
+                    if (g24[k] == 0) continue;
                     const uint32_t u = tq[k] + rq[k][j];
-                    const float frac = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u) - 1.0f;
-                    float* e = reinterpret_cast<float*>(smem + (entry_addr(u, off) - lds0));
-                    atomicAdd(e, gp[k]);
-                    atomicAdd(e + 1, gp[k] * frac);
+                    const int f23 = (int)(u & 0x7FFFFFu);
+                    // g24 * f23, both 24-bit signed: one 24 x 24-bit product
+                    const unsigned long long h =
+                        (unsigned long long)((long long)g24[k] * (long long)f23);
+                    AdjEntry* e = reinterpret_cast<AdjEntry*>(smem + (entry_addr16(u, off) - lds0));
+                    atomicAdd(&e->g, gG[k]);
+                    atomicAdd(&e->h, h);
                 }
             }
             __syncthreads();
@@ -114,22 +147,41 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                 if (c >= a.C) continue;
                 const int A0 = (at + b_tab[j]) & ~7;
                 const int s = A0 + e;
-                const float2* wj = win + j * slot;
-                float v = 0.0f;
-                if (e < a.nst && s >= 0 && s <= a.S - 2) v += wj[e].x - wj[e].y;
-                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += wj[e - 1].y;
+                const AdjEntry* wj = win + j * slot;
+                long long v = 0;
+                if (e < a.nst && s >= 0 && s <= a.S - 2)
+                    v += (long long)wj[e].g - (long long)wj[e].h;
+                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)wj[e - 1].h;
                 const size_t sl = slot_of(t, c);
-                a.ws_win[sl * ne + e] = v;
+                a.ws_win[sl * ne + e] = (float)((double)v * unscale);
                 if (e == 0) a.ws_a0[sl] = A0;
             }
             __syncthreads();
             for (int w = tid; w < kChunk * a.nst; w += NT) {
                 const int j = w / a.nst;
-                win[j * slot + (w - j * a.nst)] = make_float2(0.0f, 0.0f);
+                win[j * slot + (w - j * a.nst)] = AdjEntry{0ull, 0ull};
             }
             __syncthreads();  // windows are zero before the next pass scatters
         }
     }
+}
+
+// Stage 0: largest |g| of each frame, one workgroup per frame, fixed order.
+constexpr int kMaxThreads = 1024;
+
+__global__ void __launch_bounds__(kMaxThreads)
+    absmax_kernel(const float* __restrict__ g, size_t n, float* __restrict__ out) {
+    __shared__ float red[kMaxThreads];
+    const float* gf = g + (size_t)blockIdx.x * n;
+    float m = 0.0f;
+    for (size_t i = threadIdx.x; i < n; i += kMaxThreads) m = fmaxf(m, fabsf(gf[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = kMaxThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Stage 2: lane = RF sample s of row (t, c); the sum over tiles in tile
@@ -213,6 +265,11 @@ hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t
                               hipStream_t s) {
     return mode == 1 ? launch_adj_shape<1>(nt, px, a, lds_bytes, s)
                      : launch_adj_shape<0>(nt, px, a, lds_bytes, s);
+}
+
+hipError_t launch_absmax(const float* g, int frames, size_t n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)frames), dim3(kMaxThreads), 0, s, g, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,

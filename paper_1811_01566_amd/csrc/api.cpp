@@ -481,7 +481,7 @@ wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const
 // channel, tile) window (nst + 1 floats) and its first sample (int).
 size_t adjoint_ws_bytes(const wf_acq* acq, const TilePlan& tp) {
     const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
-    return slots * (size_t)(tp.nst + 1) * 4 + slots * 4 + 256;
+    return slots * (size_t)(tp.nst + 1) * 4 + slots * 4 + 256 + 256;  // + max |g|
 }
 
 wf_status wf_das_adjoint_workspace(int32_t mode, const wf_probe* probe, const wf_acq* acq,
@@ -537,12 +537,20 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     a.ntiles = tp.ntz * tp.ntx;
     a.ws_win = static_cast<float*>(workspace);
     a.ws_a0 = reinterpret_cast<int*>(static_cast<char*>(workspace) + slots * (tp.nst + 1) * 4);
+    float* gmax = reinterpret_cast<float*>(
+        (reinterpret_cast<uintptr_t>(a.ws_a0 + slots) + 255) & ~(uintptr_t)255);
+    a.ws_gmax = gmax;
     a.F = 1;  // one frame per launch pair: the workspace holds one frame
-    const size_t lds = tp.lds - (size_t)wf::kChunk * tp.slot * 8;  // one window buffer
+    // one buffer of 16-byte (G, H) entries: the bytes of the forward's two
+    // buffers of 8-byte entries
+    const size_t lds = tp.lds;
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
     for (int f = 0; f < acq->n_frames; ++f) {
         a.g = g + (size_t)f * grid->nz * grid->nx;
-        hipError_t e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
+        hipError_t e = wf::launch_absmax(a.g, 1, (size_t)grid->nz * grid->nx, gmax,
+                                         (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
         if (e == hipSuccess)
             e = wf::launch_adjoint_reduce(a.ws_win, a.ws_a0, grad_rf + (size_t)f * frame_rf,
                                           acq->n_tx * acq->n_ch, a.ntiles, tp.nst + 1, acq->n_s,

@@ -70,19 +70,22 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
 
     PixelSet<PX> p;
     pixel_set<NT, PX, false>(a, g, p);
-    // g rounded to 24 bits of the frame maximum: |g24| <= 2^23
+    // g rounded to 24 bits of the frame maximum: |g24| <= 2^23 - 1
     const float gmax = a.ws_gmax[frame];
-    const float to24 = gmax > 0.0f ? 8388608.0f / gmax : 0.0f;
+    const float to24 = gmax > 0.0f ? 8388607.0f / gmax : 0.0f;
     int g24[PX];
     unsigned long long gG[PX];  // G increment: g24 * 2^23
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
         const float gv = p.valid[k] ? a.g[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] : 0.0f;
-        g24[k] = ((int)rintf(gv * to24) << 8) >> 8;  // |value| <= 2^23: the shift keeps it
+        // |value| <= 2^23 - 1 (the product is rounded down to float at
+        // most to 2^23 - 1 + ulp/2 < 2^23), so the 24-bit sign extension
+        // keeps it and tells the compiler it is a 24-bit operand
+        g24[k] = ((int)rintf(fminf(fmaxf(gv * to24, -8388607.0f), 8388607.0f)) << 8) >> 8;
         gG[k] = (unsigned long long)((long long)g24[k] << kQBits);
     }
-    // fixed point -> float: 2^-23 (fraction) * gmax / 2^23 (g24)
-    const double unscale = (double)gmax * (1.0 / 70368744177664.0);  // 2^-46
+    // fixed point -> float: 2^-23 (fraction) * gmax / (2^23 - 1) (g24)
+    const double unscale = (double)gmax / (8388607.0 * 8388608.0);
     const int ne = a.nst + 1;  // samples a window can touch
     // workspace slots of (transmit t, channel c) for this tile
     auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };

@@ -36,6 +36,8 @@
 namespace wf {
 namespace {
 
+constexpr int kFlushLanes = 256;  // entries per flush row (power of two)
+
 // Window entry of the adjoint: 64-bit fixed-point G and H (scale 2^23 g24).
 struct AdjEntry {
     unsigned long long g, h;
@@ -143,11 +145,14 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             __syncthreads();
 
             // ---- flush: sample A0 + e of every window to the workspace ------
-            for (int w = tid; w < kChunk * ne; w += NT) {
-                const int j = w / ne;
-                const int e = w - j * ne;
+            // (lane -> entry e = e0 + lane % 256, channel j = lane / 256 + ...:
+            // consecutive lanes store consecutive workspace words)
+            for (int w = tid; w < kChunk * kFlushLanes * ((ne + kFlushLanes - 1) / kFlushLanes);
+                 w += NT) {
+                const int j = (w / kFlushLanes) & (kChunk - 1);
+                const int e = (w & (kFlushLanes - 1)) + kFlushLanes * (w / (kFlushLanes * kChunk));
                 const int c = c0 + j;
-                if (c >= a.C) continue;
+                if (c >= a.C || e >= ne) continue;
                 const int A0 = (at + b_tab[j]) & ~7;
                 const int s = A0 + e;
                 const AdjEntry* wj = win + j * slot;
@@ -160,52 +165,78 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                 if (e == 0) a.ws_a0[sl] = A0;
             }
             __syncthreads();
-            for (int w = tid; w < kChunk * a.nst; w += NT) {
-                const int j = w / a.nst;
-                win[j * slot + (w - j * a.nst)] = AdjEntry{0ull, 0ull};
-            }
+            for (int w = tid; w < kChunk * slot; w += NT) win[w] = AdjEntry{0ull, 0ull};
             __syncthreads();  // windows are zero before the next pass scatters
         }
     }
 }
 
-// Stage 0: largest |g| of each frame, one workgroup per frame, fixed order.
-constexpr int kMaxThreads = 1024;
+// Stage 0: largest |g| of the frame.  Non-negative floats order like their
+// bit patterns, so workgroup maxima combine with an integer atomic max into
+// a word cleared by fill_kernel (no memset: the call may be captured).
+constexpr int kMaxThreads = 256;
 
 __global__ void __launch_bounds__(kMaxThreads)
-    absmax_kernel(const float* __restrict__ g, size_t n, float* __restrict__ out) {
+    absmax_kernel(const float* __restrict__ g, size_t n, unsigned* __restrict__ out) {
     __shared__ float red[kMaxThreads];
-    const float* gf = g + (size_t)blockIdx.x * n;
     float m = 0.0f;
-    for (size_t i = threadIdx.x; i < n; i += kMaxThreads) m = fmaxf(m, fabsf(gf[i]));
+    for (size_t i = (size_t)blockIdx.x * kMaxThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kMaxThreads)
+        m = fmaxf(m, fabsf(g[i]));
     red[threadIdx.x] = m;
     __syncthreads();
     for (int h = kMaxThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
 }
 
 // Stage 2: lane = RF sample s of row (t, c); the sum over tiles in tile
-// order of the window entries that land on s.
+// order of the window entries that land on s.  The window starts of the row
+// are staged in LDS; tiles go in batches of 8 whose loads fly together, and a
+// batch none of whose windows meets the workgroup's 256 samples is skipped
+// by the whole workgroup (tiles are numbered down each column of tiles, so
+// the windows that meet a block of samples are a few neighbours).
 constexpr int kRedThreads = 256;
+constexpr int kRedBatch = 8;
+constexpr int kRedStage = 4096;  // multiple of kRedBatch
 
 __global__ void __launch_bounds__(kRedThreads)
     adjoint_reduce_kernel(const float* __restrict__ ws_win, const int* __restrict__ ws_a0,
                           float* __restrict__ grad, int ntiles, int ne, int S) {
+    __shared__ int a0s[kRedStage];  // window starts of kRedStage tiles
     const size_t row = blockIdx.x;
     const int s_lo = blockIdx.y * kRedThreads;
     const int s = s_lo + (int)threadIdx.x;
-    const int* a0r = ws_a0 + row * ntiles;
     const float* wr = ws_win + row * ntiles * (size_t)ne;
     float acc = 0.0f;
-    for (int k = 0; k < ntiles; ++k) {
-        const int A0 = __builtin_amdgcn_readfirstlane(a0r[k]);
-        // scalar test: does the window [A0, A0 + ne) meet [s_lo, s_lo + 256)?
-        if (A0 == kNoWindow || A0 + ne <= s_lo || A0 >= s_lo + kRedThreads) continue;
-        const int e = s - A0;
-        if (e >= 0 && e < ne) acc += wr[(size_t)k * ne + e];
+    for (int k0 = 0; k0 < ntiles; k0 += kRedStage) {
+        __syncthreads();  // the previous stage's readers are done
+        for (int k = threadIdx.x; k < kRedStage; k += kRedThreads)
+            a0s[k] = k0 + k < ntiles ? ws_a0[row * ntiles + k0 + k] : kNoWindow;
+        __syncthreads();
+        const int nb = (min(kRedStage, ntiles - k0) + kRedBatch - 1) / kRedBatch;
+        for (int b = 0; b < nb; ++b) {
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < kRedBatch; ++i) {
+                const int A0 = a0s[b * kRedBatch + i];
+                any |= (A0 != kNoWindow) && (A0 + ne > s_lo) && (A0 < s_lo + kRedThreads);
+            }
+            if (!__builtin_amdgcn_readfirstlane((int)any)) continue;  // same for every lane
+            float v[kRedBatch];
+#pragma unroll
+            for (int i = 0; i < kRedBatch; ++i) {
+                const int k = b * kRedBatch + i;
+                const int A0 = a0s[k];
+                const int e = s - A0;
+                v[i] = (A0 != kNoWindow && e >= 0 && e < ne)
+                           ? wr[(size_t)(k0 + k) * ne + e] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < kRedBatch; ++i) acc += v[i];
+        }
     }
     if (s < S) grad[row * S + s] = acc;
 }
@@ -270,8 +301,12 @@ hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t
                      : launch_adj_shape<0>(nt, px, a, lds_bytes, s);
 }
 
-hipError_t launch_absmax(const float* g, int frames, size_t n, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)frames), dim3(kMaxThreads), 0, s, g, n, out);
+hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, out, (size_t)1, 0.0f);
+    size_t blocks = (n + kMaxThreads * 8 - 1) / (kMaxThreads * 8);
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)blocks), dim3(kMaxThreads), 0, s, g, n,
+                       reinterpret_cast<unsigned*>(out));
     return hipGetLastError();
 }
 

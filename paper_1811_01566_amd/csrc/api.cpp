@@ -547,7 +547,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
     for (int f = 0; f < acq->n_frames; ++f) {
         a.g = g + (size_t)f * grid->nz * grid->nx;
-        hipError_t e = wf::launch_absmax(a.g, 1, (size_t)grid->nz * grid->nx, gmax,
+        hipError_t e = wf::launch_absmax(a.g, (size_t)grid->nz * grid->nx, gmax,
                                          (hipStream_t)stream);
         if (e == hipSuccess)
             e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);

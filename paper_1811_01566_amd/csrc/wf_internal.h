@@ -94,7 +94,7 @@ hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, cons
                            size_t lds_bytes, hipStream_t s);
 hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
                               hipStream_t s);
-hipError_t launch_absmax(const float* g, int frames, size_t n, float* out, hipStream_t s);
+hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s);
 hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,
                                  int ntiles, int ne, int S, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);

@@ -265,7 +265,9 @@ wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, cons
  * mx = (nx - wx) / sx + 1; E[X^p] is the mean of env^p over the window.
  *   env  DEVICE float [F][nz][nx] (the linear envelope, e.g. wf_envelope's).
  *   out  DEVICE float [F][3][mz][mx] (p = 1, 2, 3); must not overlap env.
- * 1 <= wz <= nz, 1 <= wx <= nx, sz, sx >= 1, nx <= 4096.  Deterministic.
+ * 1 <= wz <= nz, 1 <= wx <= nx, sz, sx >= 1; WF_ERR_UNSUPPORTED when
+ * 12 ((min(64, mx) - 1) sx + wx) exceeds 160 KB (the column sums of 64
+ * windows are kept in LDS).  Deterministic.
  */
 wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx, int32_t wz,
                      int32_t wx, int32_t sz, int32_t sx, float* out, void* stream);

@@ -719,12 +719,15 @@ wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx,
     wf_status st = check_image(env, n_frames, nz, nx, "env");
     if (st != WF_OK) return st;
     if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
-    if (nx > 4096) return fail(WF_ERR_UNSUPPORTED, "nx=%d is above 4096", nx);
     if (wz < 1 || wz > nz || wx < 1 || wx > nx)
         return fail(WF_ERR_INVALID_ARG, "window %dx%d does not fit the %dx%d frame", wz, wx, nz,
                     nx);
     if (sz < 1 || sx < 1) return fail(WF_ERR_INVALID_ARG, "strides must be >= 1");
     const int mz = (nz - wz) / sz + 1, mx = (nx - wx) / sx + 1;
+    // column sums of one workgroup (64 window columns) live in LDS
+    if (12.0 * ((double)(std::min(64, mx) - 1) * sx + wx) > 163840.0)
+        return fail(WF_ERR_UNSUPPORTED, "63 x sx + wx = %lld columns exceed the LDS of a workgroup",
+                    (long long)(std::min(64, mx) - 1) * sx + wx);
     if (overlaps(env, (size_t)n_frames * nz * nx * 4, out, (size_t)n_frames * 3 * mz * mx * 4))
         return fail(WF_ERR_INVALID_ARG, "out overlaps env");
     hipError_t e = wf::launch_moments(env, n_frames, nz, nx, wz, wx, sz, sx, mz, mx, out,

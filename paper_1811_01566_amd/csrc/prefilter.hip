@@ -21,10 +21,11 @@
 //
 // K7 (qUS moment maps, Fig. 3: slice -> E[X], E[X^2], E[X^3]).  Window
 // wz x wx at origins (i sz, j sx), whole windows only.  One workgroup per
-// (window row i, frame): the lanes first sum env, env^2, env^3 down the wz
-// rows of every needed column (reads coalesced along x), keep the column
-// sums in LDS, then each lane adds wx column sums for its windows and
-// divides by wz wx.  Fixed summation order: deterministic.
+// (window row i, frame, block of 64 window columns): the lanes first sum
+// env, env^2, env^3 down the wz rows of every input column the block uses
+// (reads coalesced along x, 8 rows in flight), keep the column sums in LDS,
+// then each lane adds wx column sums for its window and divides by wz wx.
+// Fixed summation order: deterministic.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -145,21 +146,26 @@ hipError_t launch_fir_t(const RT* rf, long long n_rec, int S, int kp, const FirT
     return hipGetLastError();
 }
 
-constexpr int kMomThreads = 256;
+constexpr int kMomThreads = 128;
+constexpr int kMomCols = 64;  // output columns per workgroup
 
 __global__ void __launch_bounds__(kMomThreads)
     moments_kernel(const float* __restrict__ env, float* __restrict__ out, int nz, int nx,
                    int wz, int wx, int sz, int sx, int mz, int mx) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int i = blockIdx.x;
+    const int i = blockIdx.x;  // window row
     const int f = blockIdx.y;
-    const int ncol = (mx - 1) * sx + wx;  // columns some window uses
+    const int j0 = blockIdx.z * kMomCols;  // first output column of this workgroup
+    const int jn = min(kMomCols, mx - j0);
+    const int xb = j0 * sx;                 // first input column used
+    const int ncol = (jn - 1) * sx + wx;    // input columns used
     float* v1 = reinterpret_cast<float*>(smem);
     float* v2 = v1 + ncol;
     float* v3 = v2 + ncol;
-    const float* e = env + ((size_t)f * nz + (size_t)i * sz) * nx;
+    const float* e = env + ((size_t)f * nz + (size_t)i * sz) * nx + xb;
     for (int x = threadIdx.x; x < ncol; x += kMomThreads) {
         float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll 8
         for (int z = 0; z < wz; ++z) {
             const float v = e[(size_t)z * nx + x];
             const float q = v * v;
@@ -174,8 +180,8 @@ __global__ void __launch_bounds__(kMomThreads)
     __syncthreads();
     const float cnt = (float)wz * (float)wx;
     const size_t plane = (size_t)mz * mx;
-    float* o = out + (size_t)f * 3 * plane + (size_t)i * mx;
-    for (int j = threadIdx.x; j < mx; j += kMomThreads) {
+    float* o = out + (size_t)f * 3 * plane + (size_t)i * mx + j0;
+    for (int j = threadIdx.x; j < jn; j += kMomThreads) {
         float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
         const int x0 = j * sx;
         for (int x = x0; x < x0 + wx; ++x) {
@@ -202,9 +208,16 @@ hipError_t launch_fir(int dtype, const void* rf, long long n_rec, int S, int kp,
 
 hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int wx, int sz,
                           int sx, int mz, int mx, float* out, hipStream_t s) {
-    const size_t lds = 3 * sizeof(float) * (size_t)((mx - 1) * sx + wx);
-    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)mz, (unsigned)F), dim3(kMomThreads), lds, s,
-                       env, out, nz, nx, wz, wx, sz, sx, mz, mx);
+    const int blocks = (mx + kMomCols - 1) / kMomCols;
+    const size_t lds = 3 * sizeof(float) * (size_t)(min(kMomCols, mx) - 1) * sx +
+                       3 * sizeof(float) * (size_t)wx;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(moments_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(moments_kernel, dim3((unsigned)mz, (unsigned)F, (unsigned)blocks),
+                       dim3(kMomThreads), lds, s, env, out, nz, nx, wz, wx, sz, sx, mz, mx);
     return hipGetLastError();
 }
 

@@ -2,11 +2,12 @@
 // Fig. 2: Analytic Signal -> Absolute Value -> Dynamic Adjustment; Hilbert
 // transform by FFT, Sec. II-B; dB clip, Sec. III).
 //
-// K3: one workgroup per pair of image columns.  Each column is an nz-point
-// complex FFT in LDS: a decimation-in-frequency forward pass (natural order
-// in, bit-reversed out), the one-sided multiplier applied at bit-reversed
+// K3: one workgroup per image column.  The column is an nz-point complex
+// FFT in LDS: a decimation-in-frequency forward pass (natural order in,
+// bit-reversed out), the one-sided multiplier applied at bit-reversed
 // positions, and a decimation-in-time inverse pass (bit-reversed in,
-// natural out), so no permutation pass is needed.  Twiddles come from the
+// natural out), so no permutation pass is needed; radix-2 stages run two at
+// a time (4 points per lane in registers between barriers).  Twiddles come from the
 // device library's sincospi, once per workgroup.  The kernel writes the
 // envelope and the maximum of each column; the frame maximum is reduced
 // from the column maxima by K4, so no atomics and no memset are needed and
@@ -31,110 +32,127 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// cols: columns per workgroup (1 or 2); log_n: log2(nz)
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+}
+__device__ __forceinline__ float2 cmul_conj(float2 a, float2 w) {  // a * conj(w)
+    return make_float2(fmaf(a.x, w.x, a.y * w.y), fmaf(a.y, w.x, -a.x * w.y));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// One workgroup per column (and frame); log_n = log2(nz).  Radix-2
+// stages are fused in pairs (two spans per pass through LDS, 4 points per
+// lane in registers), halving the barriers; an odd stage count leaves one
+// single stage (the first forward one, the last inverse one).
 __global__ void __launch_bounds__(kEnvThreads)
-    envelope_kernel(const float* bf, float* env,
-                    float* __restrict__ col_max, int nz, int nx, int log_n, int cols) {
+    envelope_kernel(const float* bf, float* env, float* __restrict__ col_max, int nz, int nx,
+                    int log_n) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = nz;
     const int half = n >> 1;
-    float2* tw = reinterpret_cast<float2*>(smem);              // [n/2]
-    float2* buf = reinterpret_cast<float2*>(smem) + (half > 0 ? half : 1);  // [cols][n]
-    __shared__ float red[kEnvThreads / 64][2];
+    float2* tw = reinterpret_cast<float2*>(smem);                 // [n/2]
+    float2* col = tw + (half > 0 ? half : 1);                     // [n]
+    __shared__ float red[kEnvThreads / 64];
 
     const int tid = threadIdx.x;
+    const int x = blockIdx.x;
     const int f = blockIdx.y;
-    const int xb = blockIdx.x * cols;
-    const float* src = bf + (size_t)f * nz * nx;
-    float* dst = env + (size_t)f * nz * nx;
+    const float* src = bf + (size_t)f * nz * nx + x;
+    float* dst = env + (size_t)f * nz * nx + x;
 
     // W^k = exp(-2 pi i k / n)
     for (int k = tid; k < half; k += kEnvThreads) {
-        float s, c;
-        sincospif(-2.0f * (float)k / (float)n, &s, &c);
-        tw[k] = make_float2(c, s);
+        float sn, cs;
+        sincospif(-2.0f * (float)k / (float)n, &sn, &cs);
+        tw[k] = make_float2(cs, sn);
     }
-    for (int i = tid; i < cols * n; i += kEnvThreads) {
-        const int c = i % cols;
-        const int z = i / cols;
-        const int x = xb + c;
-        const float v = (x < nx) ? src[(size_t)z * nx + x] : 0.0f;
-        buf[c * n + z] = make_float2(v, 0.0f);
-    }
+    for (int z = tid; z < n; z += kEnvThreads) col[z] = make_float2(src[(size_t)z * nx], 0.0f);
     __syncthreads();
 
-    const int nbf = cols * half;  // butterflies per stage
-    // forward DIF: span h = n/2 .. 1
-    for (int h = half; h >= 1; h >>= 1) {
-        const int tstride = half / h;
-        for (int b = tid; b < nbf; b += kEnvThreads) {
-            const int c = b / half;
-            const int bb = b - c * half;
-            const int pos = bb & (h - 1);
-            const int i = ((bb - pos) << 1) + pos;
-            float2* col = buf + c * n;
-            const float2 x0 = col[i], x1 = col[i + h];
-            const float2 w = tw[pos * tstride];
-            const float dr = x0.x - x1.x, di = x0.y - x1.y;
-            col[i] = make_float2(x0.x + x1.x, x0.y + x1.y);
-            col[i + h] = make_float2(fmaf(dr, w.x, -di * w.y), fmaf(dr, w.y, di * w.x));
+    // ---- forward DIF, spans n/2 .. 1 ------------------------------------
+    int h = half;
+    if (log_n & 1) {  // single stage of span n/2
+        for (int b = tid; b < half; b += kEnvThreads) {
+            const float2 x0 = col[b], x1 = col[b + h];
+            col[b] = cadd(x0, x1);
+            col[b + h] = cmul(csub(x0, x1), tw[b]);
+        }
+        __syncthreads();
+        h >>= 1;
+    }
+    for (; h >= 2; h >>= 2) {  // spans h and h/2 in one pass
+        const int q = h >> 1, ts = half / h;
+        for (int g = tid; g < (n >> 2); g += kEnvThreads) {
+            const int pos = g & (q - 1);
+            const int i0 = ((g - pos) << 2) + pos;  // block of 2h
+            float2 a0 = col[i0], a1 = col[i0 + q], a2 = col[i0 + h], a3 = col[i0 + h + q];
+            const float2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), tw[pos * ts]);
+            const float2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), tw[(pos + q) * ts]);
+            const float2 w2 = tw[pos * 2 * ts];
+            col[i0] = cadd(b0, b1);
+            col[i0 + q] = cmul(csub(b0, b1), w2);
+            col[i0 + h] = cadd(b2, b3);
+            col[i0 + h + q] = cmul(csub(b2, b3), w2);
         }
         __syncthreads();
     }
     // one-sided spectrum: position p holds bin k = bitrev(p)
-    for (int i = tid; i < cols * n; i += kEnvThreads) {
-        const int c = i / n;
-        const int p = i - c * n;
-        const int k = (int)(__brev((unsigned)p) >> (32 - log_n));
-        const float g = (k == 0 || k == half) ? 1.0f : (k < half ? 2.0f : 0.0f);
-        float2 v = buf[c * n + p];
-        buf[c * n + p] = make_float2(v.x * g, v.y * g);
+    for (int p = tid; p < n; p += kEnvThreads) {
+        const int k = log_n > 0 ? (int)(__brev((unsigned)p) >> (32 - log_n)) : 0;
+        const float gk = (k == 0 || k == half) ? 1.0f : (k < half ? 2.0f : 0.0f);
+        const float2 v = col[p];
+        col[p] = make_float2(v.x * gk, v.y * gk);
     }
     __syncthreads();
-    // inverse DIT with conjugate twiddles: span h = 1 .. n/2
-    for (int h = 1; h <= half; h <<= 1) {
-        const int tstride = half / h;
-        for (int b = tid; b < nbf; b += kEnvThreads) {
-            const int c = b / half;
-            const int bb = b - c * half;
-            const int pos = bb & (h - 1);
-            const int i = ((bb - pos) << 1) + pos;
-            float2* col = buf + c * n;
-            const float2 w = tw[pos * tstride];
-            const float2 x1 = col[i + h];
-            // t = conj(w) * x1
-            const float tr = fmaf(x1.x, w.x, x1.y * w.y);
-            const float ti = fmaf(x1.y, w.x, -x1.x * w.y);
-            const float2 x0 = col[i];
-            col[i] = make_float2(x0.x + tr, x0.y + ti);
-            col[i + h] = make_float2(x0.x - tr, x0.y - ti);
+    // ---- inverse DIT with conjugate twiddles, spans 1 .. n/2 -------------
+    h = 1;
+    const int pairs = log_n >> 1;
+    for (int st = 0; st < pairs; ++st, h <<= 2) {  // spans h and 2h in one pass
+        const int ts = half / h, ts2 = ts >> 1;
+        for (int g = tid; g < (n >> 2); g += kEnvThreads) {
+            const int pos = g & (h - 1);
+            const int i0 = ((g - pos) << 2) + pos;  // block of 4h
+            const float2 a0 = col[i0], a1 = col[i0 + h], a2 = col[i0 + 2 * h],
+                         a3 = col[i0 + 3 * h];
+            const float2 w1 = tw[pos * ts];
+            const float2 t1 = cmul_conj(a1, w1), t3 = cmul_conj(a3, w1);
+            const float2 b0 = cadd(a0, t1), b1 = csub(a0, t1);
+            const float2 b2 = cadd(a2, t3), b3 = csub(a2, t3);
+            const float2 u2 = cmul_conj(b2, tw[pos * ts2]);
+            const float2 u3 = cmul_conj(b3, tw[(pos + h) * ts2]);
+            col[i0] = cadd(b0, u2);
+            col[i0 + 2 * h] = csub(b0, u2);
+            col[i0 + h] = cadd(b1, u3);
+            col[i0 + 3 * h] = csub(b1, u3);
         }
         __syncthreads();
     }
-    // modulus, store, column maxima
+    if (log_n & 1) {  // last single stage, span n/2
+        for (int b = tid; b < half; b += kEnvThreads) {
+            const float2 t = cmul_conj(col[b + half], tw[b]);
+            const float2 x0 = col[b];
+            col[b] = cadd(x0, t);
+            col[b + half] = csub(x0, t);
+        }
+        __syncthreads();
+    }
+    // modulus, store, column maximum
     const float inv_n = 1.0f / (float)n;
-    float m0 = 0.0f, m1 = 0.0f;
-    for (int i = tid; i < cols * n; i += kEnvThreads) {
-        const int c = i % cols;
-        const int z = i / cols;
-        const int x = xb + c;
-        const float2 v = buf[c * n + z];
+    float m = 0.0f;
+    for (int z = tid; z < n; z += kEnvThreads) {
+        const float2 v = col[z];
         const float e = sqrtf(fmaf(v.x, v.x, v.y * v.y)) * inv_n;
-        if (x < nx) dst[(size_t)z * nx + x] = e;
-        if (c == 0) m0 = fmaxf(m0, e); else m1 = fmaxf(m1, e);
+        dst[(size_t)z * nx] = e;
+        m = fmaxf(m, e);
     }
-    const int lane = tid & 63, wv = tid >> 6;
-    m0 = wave_max(m0);
-    m1 = wave_max(m1);
-    if (lane == 0) {
-        red[wv][0] = m0;
-        red[wv][1] = m1;
-    }
+    m = wave_max(m);
+    if ((tid & 63) == 0) red[tid >> 6] = m;
     __syncthreads();
-    if (tid < cols && xb + tid < nx) {
-        float r = red[0][tid];
-        for (int q = 1; q < kEnvThreads / 64; ++q) r = fmaxf(r, red[q][tid]);
-        col_max[(size_t)f * nx + xb + tid] = r;
+    if (tid == 0) {
+        float r = red[0];
+        for (int w = 1; w < kEnvThreads / 64; ++w) r = fmaxf(r, red[w]);
+        col_max[(size_t)f * nx + x] = r;
     }
 }
 
@@ -174,11 +192,10 @@ hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, f
                            hipStream_t s) {
     int log_n = 0;
     while ((1 << log_n) < nz) ++log_n;
-    const int cols = (nz <= 2048) ? 2 : 1;
-    const size_t lds = (size_t)((nz / 2 > 0 ? nz / 2 : 1) + cols * nz) * sizeof(float2);
-    dim3 grid((unsigned)((nx + cols - 1) / cols), (unsigned)F);
-    hipLaunchKernelGGL(envelope_kernel, grid, dim3(kEnvThreads), lds, s, bf, env, col_max, nz,
-                       nx, log_n, cols);
+    const size_t lds = (size_t)((nz / 2 > 0 ? nz / 2 : 1) + nz) * sizeof(float2);
+    dim3 grid((unsigned)nx, (unsigned)F);
+    hipLaunchKernelGGL(envelope_kernel, grid, dim3(kEnvThreads), lds, s, bf, env, col_max, nz, nx,
+                       log_n);
     return hipGetLastError();
 }
 

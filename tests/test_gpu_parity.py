@@ -166,7 +166,8 @@ def test_delays_full_size_pwi(wf_gpu):
 # envelope / log compression
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("nz,nx,frames", [(64, 5, 1), (1024, 33, 2), (4096, 3, 1), (2, 4, 1)])
+@pytest.mark.parametrize("nz,nx,frames", [(64, 5, 1), (1024, 33, 2), (4096, 3, 1), (2, 4, 1),
+                                           (512, 7, 2), (2048, 5, 1), (4, 9, 1)])
 def test_envelope_matches_oracle(wf_gpu, nz, nx, frames):
     torch = _torch()
     rng = np.random.default_rng(nz + nx)

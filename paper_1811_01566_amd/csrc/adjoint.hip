@@ -193,46 +193,62 @@ __global__ void __launch_bounds__(kMaxThreads)
 }
 
 // Stage 2: lane = RF sample s of row (t, c); the sum over tiles in tile
-// order of the window entries that land on s.  The window starts of the row
-// are staged in LDS; tiles go in batches of 8 whose loads fly together, and a
-// batch none of whose windows meets the workgroup's 256 samples is skipped
-// by the whole workgroup (tiles are numbered down each column of tiles, so
-// the windows that meet a block of samples are a few neighbours).
+// order of the window entries that land on s.  The tiles are taken 256 at a
+// time: each lane tests one tile's window against the workgroup's 256
+// samples, the overlapping tiles are compacted in tile order into an LDS
+// list (wave ballots and a prefix over the 4 waves), and the list is summed
+// in batches of 8 whose loads fly together.
 constexpr int kRedThreads = 256;
 constexpr int kRedBatch = 8;
-constexpr int kRedStage = 4096;  // multiple of kRedBatch
 
 __global__ void __launch_bounds__(kRedThreads)
     adjoint_reduce_kernel(const float* __restrict__ ws_win, const int* __restrict__ ws_a0,
                           float* __restrict__ grad, int ntiles, int ne, int S) {
-    __shared__ int a0s[kRedStage];  // window starts of kRedStage tiles
+    __shared__ int list_k[kRedThreads + kRedBatch];   // overlapping tiles, in order
+    __shared__ int list_a0[kRedThreads + kRedBatch];  // their window starts
+    __shared__ int wave_cnt[kRedThreads / 64];
     const size_t row = blockIdx.x;
     const int s_lo = blockIdx.y * kRedThreads;
-    const int s = s_lo + (int)threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int s = s_lo + tid;
+    const int* a0r = ws_a0 + row * ntiles;
     const float* wr = ws_win + row * ntiles * (size_t)ne;
     float acc = 0.0f;
-    for (int k0 = 0; k0 < ntiles; k0 += kRedStage) {
-        __syncthreads();  // the previous stage's readers are done
-        for (int k = threadIdx.x; k < kRedStage; k += kRedThreads)
-            a0s[k] = k0 + k < ntiles ? ws_a0[row * ntiles + k0 + k] : kNoWindow;
+    for (int k0 = 0; k0 < ntiles; k0 += kRedThreads) {
+        // ---- compact the tiles of [k0, k0 + 256) whose window meets the block
+        const int k = k0 + tid;
+        const int A0 = k < ntiles ? a0r[k] : kNoWindow;
+        const bool hit = (A0 != kNoWindow) && (A0 + ne > s_lo) && (A0 < s_lo + kRedThreads);
+        const unsigned long long m = __ballot(hit);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        __syncthreads();  // the previous round's list readers are done
+        if (lane == 0) wave_cnt[wave] = __popcll(m);
         __syncthreads();
-        const int nb = (min(kRedStage, ntiles - k0) + kRedBatch - 1) / kRedBatch;
-        for (int b = 0; b < nb; ++b) {
-            bool any = false;
+        int base = 0, total = 0;
 #pragma unroll
-            for (int i = 0; i < kRedBatch; ++i) {
-                const int A0 = a0s[b * kRedBatch + i];
-                any |= (A0 != kNoWindow) && (A0 + ne > s_lo) && (A0 < s_lo + kRedThreads);
-            }
-            if (!__builtin_amdgcn_readfirstlane((int)any)) continue;  // same for every lane
+        for (int w = 0; w < kRedThreads / 64; ++w) {
+            base += w < wave ? wave_cnt[w] : 0;
+            total += wave_cnt[w];
+        }
+        if (hit) {
+            list_k[base + before] = k;
+            list_a0[base + before] = A0;
+        }
+        if (tid < kRedBatch) {  // pad the last batch with entries that add 0
+            list_k[total + tid] = 0;
+            list_a0[total + tid] = kNoWindow;
+        }
+        __syncthreads();
+        // ---- sum the list in order ------------------------------------
+        for (int b = 0; b < total; b += kRedBatch) {
             float v[kRedBatch];
 #pragma unroll
             for (int i = 0; i < kRedBatch; ++i) {
-                const int k = b * kRedBatch + i;
-                const int A0 = a0s[k];
-                const int e = s - A0;
-                v[i] = (A0 != kNoWindow && e >= 0 && e < ne)
-                           ? wr[(size_t)(k0 + k) * ne + e] : 0.0f;
+                const int a0 = list_a0[b + i];
+                const int e = s - a0;
+                v[i] = (a0 != kNoWindow && e >= 0 && e < ne)
+                           ? wr[(size_t)list_k[b + i] * ne + e] : 0.0f;
             }
 #pragma unroll
             for (int i = 0; i < kRedBatch; ++i) acc += v[i];

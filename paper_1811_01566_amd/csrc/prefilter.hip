@@ -11,7 +11,9 @@
 // tests a record edge.  A lane owns 8 consecutive outputs (S % 8 == 0),
 // reads its K + 7 inputs from LDS into registers and runs 8 K FMAs with the
 // taps in scalar registers; lanes past the record's end exit (whole waves
-// when S < 2048).  The staged samples are stored with one pad word after
+// when S < 2048).  A resident grid walks the segments and loads the next
+// segment into registers while filtering the current one.  The staged
+// samples are stored with one pad word after
 // every 8, so lane i's window starts at word 9 i: 9 is odd, so neighbouring
 // lanes hit different LDS banks (a stride of 8 words would put every 4th
 // lane on the same bank).  The tap count is padded to KP in {15, 31, 63} with zeros
@@ -74,76 +76,127 @@ __device__ __forceinline__ void load8<float>(const float* p, float (&v)[8]) {
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
+// Raw staging words of one lane: chunks c = lane and lane + 256 of the
+// 264 chunks of 8 samples (only lanes < 8 have a second chunk).
+template <typename RT>
+struct FirRaw {
+    float v[2][8];
+};
+
 template <typename RT, int KP>
 __global__ void __launch_bounds__(kFirThreads)
     fir_kernel(const RT* __restrict__ rf, float* __restrict__ out, int S, int nseg,
-               const FirTaps taps) {
+               long long nblocks, const FirTaps taps) {
     constexpr int D = (KP - 1) / 2;
     constexpr int kStage = kFirBlock + 2 * kFirHalo;       // staged samples
+    constexpr int kChunks = kStage / 8;                    // 264
     constexpr int kFirst = kFirHalo - D;                   // lane's first sample - 8 lane
     constexpr int kWin = KP + kFirPerLane - 1;             // inputs a lane needs
     // sample e of the staged range lives at word e + e / 8
     __shared__ float xs[kStage + kStage / 8];
-
     const int tid = threadIdx.x;
-    const long long rec = blockIdx.x / nseg;
-    const int sb = (int)(blockIdx.x - rec * nseg) * kFirBlock;  // first output
-    const RT* row = rf + rec * S;
-    // ---- stage [sb - halo, sb + block + halo) of the record, zeros outside --
-    for (int c = tid; c < kStage / 8; c += kFirThreads) {
-        const int q = sb - kFirHalo + 8 * c;  // multiple of 8, as is S
-        float v[8];
-        if (q >= 0 && q < S) {
-            load8<RT>(row + q, v);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = 0.0f;
-        }
-        float* d = xs + 9 * c;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) d[i] = v[i];
-    }
-    __syncthreads();
 
-    const int s0 = sb + kFirPerLane * tid;
-    if (s0 >= S) return;
-    // input m (record position s0 - D + m) is staged sample e = 8 lane +
-    // kFirst + m, at word e + e / 8 = 9 lane + (kFirst + m) + (kFirst + m) / 8
-    constexpr int kLead = 0;
-    float xw[kWin];
-    const float* src = xs + 9 * tid;
+    // global -> registers for segment b: [sb - halo, sb + block + halo) of the
+    // record, zeros outside it
+    auto fetch = [&](long long b, FirRaw<RT>& raw) {
+        const long long rec = b / nseg;
+        const int sb = (int)(b - rec * nseg) * kFirBlock;
+        const RT* row = rf + rec * S;
 #pragma unroll
-    for (int m = 0; m < kWin; ++m) xw[m] = src[(kFirst + m) + (kFirst + m) / 8];
-    float acc[kFirPerLane];
+        for (int h = 0; h < 2; ++h) {
+            const int c = tid + h * kFirThreads;
+            const int q = sb - kFirHalo + 8 * c;  // multiple of 8, as is S
+            if (c < kChunks && q >= 0 && q < S) {
+                load8<RT>(row + q, raw.v[h]);
+            } else {
 #pragma unroll
-    for (int i = 0; i < kFirPerLane; ++i) acc[i] = 0.0f;
+                for (int i = 0; i < 8; ++i) raw.v[h][i] = 0.0f;
+            }
+        }
+    };
+
+    FirRaw<RT> raw;
+    long long b = blockIdx.x;
+    if (b < nblocks) fetch(b, raw);
+    for (; b < nblocks; b += gridDim.x) {
+        __syncthreads();  // the previous segment's readers are done
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        const float h = taps.h[k];
+        for (int h = 0; h < 2; ++h) {
+            const int c = tid + h * kFirThreads;
+            if (c < kChunks) {
+                float* d = xs + 9 * c;
 #pragma unroll
-        for (int i = 0; i < kFirPerLane; ++i)
-            acc[i] = fmaf(h, xw[kLead + i + KP - 1 - k], acc[i]);
+                for (int i = 0; i < 8; ++i) d[i] = raw.v[h][i];
+            }
+        }
+        __syncthreads();
+        // the next segment's loads fly while this one is filtered
+        if (b + gridDim.x < nblocks) fetch(b + gridDim.x, raw);
+
+        const long long rec = b / nseg;
+        const int sb = (int)(b - rec * nseg) * kFirBlock;
+        const int s0 = sb + kFirPerLane * tid;
+        if (s0 >= S) continue;
+        // input m (record position s0 - D + m) is staged sample e = 8 lane +
+        // kFirst + m, at word e + e / 8
+        float xw[kWin];
+        const float* src = xs + 9 * tid;
+#pragma unroll
+        for (int m = 0; m < kWin; ++m) xw[m] = src[(kFirst + m) + (kFirst + m) / 8];
+        float acc[kFirPerLane];
+#pragma unroll
+        for (int i = 0; i < kFirPerLane; ++i) acc[i] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const float h = taps.h[k];
+#pragma unroll
+            for (int i = 0; i < kFirPerLane; ++i)
+                acc[i] = fmaf(h, xw[i + KP - 1 - k], acc[i]);
+        }
+        float4* dst = reinterpret_cast<float4*>(out + rec * S + s0);
+        dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
     }
-    float4* dst = reinterpret_cast<float4*>(out + rec * S + s0);
-    dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+}
+
+// Workgroups of `kernel` that fit on the device at once (CUs x occupancy),
+// queried once per kernel and device.
+template <typename K>
+long long resident_blocks(K kernel) {
+    static long long cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+    if (cached[dev] == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kFirThreads, 0) !=
+                hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return 1024;
+        cached[dev] = (long long)cus * per_cu;
+    }
+    return cached[dev];
+}
+
+template <typename RT, int KP>
+hipError_t launch_fir_kp(const RT* rf, int S, int nseg, long long nblocks, const FirTaps& taps,
+                         float* out, hipStream_t s) {
+    // a resident grid walks the segments, prefetching the next one
+    const long long resident = resident_blocks(fir_kernel<RT, KP>);
+    const dim3 grid((unsigned)(nblocks < resident ? nblocks : resident));
+    hipLaunchKernelGGL((fir_kernel<RT, KP>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
+                       nblocks, taps);
+    return hipGetLastError();
 }
 
 template <typename RT>
 hipError_t launch_fir_t(const RT* rf, long long n_rec, int S, int kp, const FirTaps& taps,
                         float* out, hipStream_t s) {
     const int nseg = (S + kFirBlock - 1) / kFirBlock;
-    const dim3 grid((unsigned)(n_rec * nseg));
-    if (kp == 15)
-        hipLaunchKernelGGL((fir_kernel<RT, 15>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
-                           taps);
-    else if (kp == 31)
-        hipLaunchKernelGGL((fir_kernel<RT, 31>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
-                           taps);
-    else
-        hipLaunchKernelGGL((fir_kernel<RT, 63>), grid, dim3(kFirThreads), 0, s, rf, out, S, nseg,
-                           taps);
-    return hipGetLastError();
+    const long long nblocks = n_rec * nseg;
+    if (kp == 15) return launch_fir_kp<RT, 15>(rf, S, nseg, nblocks, taps, out, s);
+    if (kp == 31) return launch_fir_kp<RT, 31>(rf, S, nseg, nblocks, taps, out, s);
+    return launch_fir_kp<RT, 63>(rf, S, nseg, nblocks, taps, out, s);
 }
 
 constexpr int kMomThreads = 128;

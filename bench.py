@@ -303,8 +303,11 @@ def main():
     col_max = torch.empty((F, w.nx), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    wsb = wf.das_workspace_bytes(scan, w.n_s, F)
+    das_ws = torch.empty(wsb, dtype=torch.uint8, device=dev) if wsb else None
+
     def step():
-        wf.das(scan, rf, out=y)
+        wf.das(scan, rf, out=y, workspace=das_ws)
         wf.bmode(y, w.dr_db, out=out, col_max=col_max)
 
     for _ in range(args.warmup):
@@ -318,7 +321,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        wf.das(scan, rf, out=y)
+        wf.das(scan, rf, out=y, workspace=das_ws)
         ev[i][1].record(stream)
         wf.bmode(y, w.dr_db, out=out, col_max=col_max)
         ev[i][2].record(stream)
@@ -385,7 +388,7 @@ def main():
         e0.record(stream)
         wf.das_adjoint(scan, gcot, w.n_s, out=grad_rf, workspace=adj_ws)
         e1.record(stream)
-        wf.das_dydc(scan, rf, out=dydc)
+        wf.das_dydc(scan, rf, out=dydc, workspace=das_ws)
         e2.record(stream)
         torch.cuda.synchronize()
         if i >= 2:
@@ -429,7 +432,7 @@ def main():
             bufs[b].copy_(host_rf, non_blocking=True)
             copied[b].record(copy_stream)
         stream.wait_event(copied[b])
-        wf.das(scan, bufs[b], out=y)
+        wf.das(scan, bufs[b], out=y, workspace=das_ws)
         freed[b].record(stream)
         wf.bmode(y, w.dr_db, out=out, col_max=col_max)
     torch.cuda.synchronize()
@@ -468,7 +471,7 @@ def main():
             "mode": w.mode, "frames_per_step": F, "n_tx": w.n_tx, "n_ch": w.n_ch,
             "n_s": w.n_s, "grid": [w.nz, w.nx], "rf_dtype": args.rf_dtype,
             "depth_mm": [w.z_min * 1e3, w.z_max * 1e3], "f_number": w.f_number,
-            "dr_db": w.dr_db,
+            "dr_db": w.dr_db, "channel_split_workspace_bytes": wsb,
         },
         "das_gsamples_per_s": round(nominal / das_avg_s / 1e9, 2),
         "das_gsamples_per_s_active": round(act_frac * nominal / das_avg_s / 1e9, 2),

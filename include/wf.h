@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 2
+#define WF_ABI_VERSION 3
 
 typedef enum {
     WF_OK = 0,
@@ -111,24 +111,41 @@ typedef struct {
  * (acquisitions, channels, samples), Sec. III).  Transmit t fires the single
  * element tx_elem[t] (HOST [n_tx], NULL = t); the sum runs over transmits
  * and receive channels.
- *   rf   DEVICE [F][T][C][S] of acq->dtype, 16-byte aligned.
- *   out  DEVICE float [F][nz][nx] beamformed RF (real, not IQ); must not
- *        overlap rf.
+ *   rf         DEVICE [F][T][C][S] of acq->dtype, 16-byte aligned.
+ *   out        DEVICE float [F][nz][nx] beamformed RF (real, not IQ); must
+ *              not overlap rf.
+ *   workspace  optional DEVICE scratch, caller-owned, 4-byte aligned, not
+ *              overlapping rf or out.  When it holds at least the bytes
+ *              wf_das_workspace reports (> 0 only for grids with fewer
+ *              tiles than the GPU holds workgroups), the channels of each
+ *              tile are shared by several workgroups whose partial frames
+ *              are then summed in a fixed order; otherwise (NULL, or fewer
+ *              bytes) the call runs unsplit.  Both are deterministic; they
+ *              differ only in the order of the FP32 sums.
  * Returns WF_ERR_UNSUPPORTED when the pixel spacing is so coarse that no
  * tile shape keeps a tile's delay spread inside the kernel's window.
  */
 wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const wf_grid* grid, float* out,
-                      void* stream);
+                      void* workspace, uint64_t workspace_bytes, void* stream);
 
 /*
  * DAS for plane-wave imaging with coherent compounding over angles
  * (Sec. II-B).  angles_rad: HOST [n_tx] steering angles, |theta| < 80 deg.
- * tref: wf_pwi_tref.  rf and out as for wf_das_stai.
+ * tref: wf_pwi_tref.  rf, out and workspace as for wf_das_stai.
  */
 wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid,
-                     float* out, void* stream);
+                     float* out, void* workspace, uint64_t workspace_bytes, void* stream);
+
+/*
+ * Bytes of the optional workspace of wf_das_stai / wf_das_pwi / wf_das_dydc
+ * for this geometry and acq->n_frames (0: the calls never split).  Host
+ * only.  mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
+ */
+wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                           const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                           const wf_grid* grid, uint64_t* bytes);
 
 /*
  * One-way times of flight in samples as computed on the device (float-float
@@ -187,11 +204,13 @@ wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
  * this is the derivative that lets c be learned.
  *   rf    DEVICE [F][T][C][S] as for the DAS calls.
  *   dydc  DEVICE float [F][nz][nx].
+ *   workspace, workspace_bytes  as for wf_das_stai.
  * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
  */
 wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                      const wf_grid* grid, float* dydc, void* stream);
+                      const wf_grid* grid, float* dydc, void* workspace,
+                      uint64_t workspace_bytes, void* stream);
 
 /*
  * Adjoint of DAS w.r.t. the RF (the transpose of the interpolating gather):

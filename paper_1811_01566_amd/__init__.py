@@ -26,7 +26,7 @@ from ._lib import WfError, load
 
 __all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
            "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info",
-           "adjoint_workspace_bytes",
+           "adjoint_workspace_bytes", "das_workspace_bytes",
            "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd"]
 
 
@@ -151,9 +151,36 @@ def _rf_dtype(t):
 # public calls
 # ---------------------------------------------------------------------------
 
-def das(scan: Scan, rf, out=None, stream=None):
+def das_workspace_bytes(scan: Scan, n_s: int, n_frames: int = 1) -> int:
+    """Bytes of the optional DAS workspace (0: the geometry never splits)."""
+    lib = load()
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, n_frames, n_s, _lib.WF_RF_I16)
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    n = ctypes.c_uint64(0)
+    _lib.check(lib.wf_das_workspace(mode, probe, acq, tx, ang, tref, grid, ctypes.byref(n)),
+               "wf_das_workspace")
+    return int(n.value)
+
+
+def _workspace_arg(scan, ns, nf, workspace, device):
+    """(pointer, bytes) of the DAS workspace: the caller's, or a fresh one
+    when the geometry splits and none is given."""
+    torch = _torch()
+    if workspace is None:
+        need = das_workspace_bytes(scan, ns, nf)
+        if need == 0:
+            return None, 0, None
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    return (_dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+            workspace)
+
+
+def das(scan: Scan, rf, out=None, workspace=None, stream=None):
     """Delay-and-Sum of rf [F][T][C][S] (or [T][C][S]) -> float32 [F][nz][nx]
-    (or [nz][nx])."""
+    (or [nz][nx]).  `workspace` (uint8 device tensor of
+    :func:`das_workspace_bytes`) lets small grids split channels across
+    workgroups; it is allocated when not given."""
     torch = _torch()
     lib = load()
     squeeze = rf.dim() == 3
@@ -169,32 +196,35 @@ def das(scan: Scan, rf, out=None, stream=None):
         out = torch.empty((nf, g.nz, g.nx), dtype=torch.float32, device=rf.device)
     elif out.dtype != torch.float32 or out.numel() != nf * g.nz * g.nx:
         raise ValueError("out must be float32 with F*nz*nx elements")
+    if scan.mode not in ("stai", "pwi"):
+        raise ValueError(f"mode must be 'stai' or 'pwi', got {scan.mode!r}")
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
     rfp, outp, st = _dev(rf4, "rf"), _dev(out, "out"), _stream_ptr(rf4, stream)
+    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device)
     if scan.mode == "stai":
         tx = keep.arr(ctypes.c_int32, scan.tx_elem)
-        _lib.check(lib.wf_das_stai(rfp, probe, acq, tx, grid, outp, st), "wf_das_stai")
-    elif scan.mode == "pwi":
-        ang = keep.arr(ctypes.c_double, scan.angles_rad)
-        _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, outp, st),
-                   "wf_das_pwi")
+        _lib.check(lib.wf_das_stai(rfp, probe, acq, tx, grid, outp, wsp, wsb, st),
+                   "wf_das_stai")
     else:
-        raise ValueError(f"mode must be 'stai' or 'pwi', got {scan.mode!r}")
+        ang = keep.arr(ctypes.c_double, scan.angles_rad)
+        _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, outp, wsp, wsb, st),
+                   "wf_das_pwi")
+    del ws_keep  # the caching allocator keeps the block until the stream is done with it
     out = out.view(nf, g.nz, g.nx)
     return out[0] if squeeze else out
 
 
-def das_stai(rf, scan: Scan, out=None, stream=None):
+def das_stai(rf, scan: Scan, out=None, workspace=None, stream=None):
     if scan.mode != "stai":
         raise ValueError("scan.mode must be 'stai'")
-    return das(scan, rf, out, stream)
+    return das(scan, rf, out=out, workspace=workspace, stream=stream)
 
 
-def das_pwi(rf, scan: Scan, out=None, stream=None):
+def das_pwi(rf, scan: Scan, out=None, workspace=None, stream=None):
     if scan.mode != "pwi":
         raise ValueError("scan.mode must be 'pwi'")
-    return das(scan, rf, out, stream)
+    return das(scan, rf, out=out, workspace=workspace, stream=stream)
 
 
 TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
@@ -336,7 +366,7 @@ def _mode_args(scan: Scan, keep: _Keep):
     return mode, tx, ang, tref
 
 
-def das_dydc(scan: Scan, rf, out=None, stream=None):
+def das_dydc(scan: Scan, rf, out=None, workspace=None, stream=None):
     """d y / d c per pixel (forward mode), rf [F][T][C][S] -> [F][nz][nx]."""
     torch = _torch()
     lib = load()
@@ -348,8 +378,11 @@ def das_dydc(scan: Scan, rf, out=None, stream=None):
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
     mode, tx, ang, tref = _mode_args(scan, keep)
+    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device)
     _lib.check(lib.wf_das_dydc(mode, _dev(rf4, "rf"), probe, acq, tx, ang, tref, grid,
-                               _dev(out, "dydc"), _stream_ptr(rf4, stream)), "wf_das_dydc")
+                               _dev(out, "dydc"), wsp, wsb, _stream_ptr(rf4, stream)),
+               "wf_das_dydc")
+    del ws_keep
     return out
 
 

@@ -377,6 +377,9 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->ntz = tp->ntz;
     a->ntx = tp->ntx;
     a->xcd_order = (WF_DAS_XCD_ORDER && (tp->ntz * tp->ntx) % 8 == 0) ? 1 : 0;
+    a->nsplit = 1;  // no channel split unless the caller's workspace allows one
+    a->split_chunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
+    a->partial = nullptr;
     a->ng = tp->nst / 8;
     a->nst = tp->nst;
     a->slot = tp->slot;
@@ -414,9 +417,39 @@ int groups_of(const wf::DasArgs& a, const TilePlan& tp) {
 }
 
 // forward DAS (op 0) or forward-mode d y / d c (op 1)
+// Channel split for grids with few tiles: each tile's channel chunks are
+// shared by nsplit workgroups that write partial frames, summed afterwards
+// in split order.  The split depends on the tile count only (not on the
+// number of frames), so a batch gives the same bits as its frames one by
+// one.  The target is the number of workgroups the GPU holds at once
+// (256 CUs x the workgroups of this shape one CU holds).
+struct SplitPlan {
+    int nsplit = 1, chunks = 1;
+};
+
+SplitPlan plan_split(const TilePlan& tp, const wf_acq* acq) {
+    SplitPlan sp;
+    const int nchunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
+    sp.chunks = nchunks;
+    const long long tiles = (long long)tp.ntz * tp.ntx;
+    const int by_waves = std::max(1, 16 / (tp.threads / 64));
+    const int by_lds = std::max(1, (int)(kLdsHard / std::max<size_t>(tp.lds, 1)));
+    const long long target = 256LL * std::min(by_waves, by_lds);
+    if (tiles >= target || nchunks < 2) return sp;
+    const int want = (int)std::min<long long>(nchunks, (target + tiles - 1) / tiles);
+    sp.chunks = (nchunks + want - 1) / want;
+    sp.nsplit = (nchunks + sp.chunks - 1) / sp.chunks;
+    return sp;
+}
+
+size_t split_ws_bytes(const SplitPlan& sp, const wf_acq* acq, const wf_grid* grid) {
+    return sp.nsplit > 1 ? (size_t)sp.nsplit * acq->n_frames * grid->nz * grid->nx * 4 : 0;
+}
+
 wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const int32_t* tx_elem, const double* angles, int32_t tref,
-                     const wf_grid* grid, float* out, void* stream) {
+                     const wf_grid* grid, float* out, void* workspace, uint64_t ws_bytes,
+                     void* stream) {
     wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
     if ((st = check_rf(rf, acq)) != WF_OK) return st;
@@ -431,10 +464,24 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
         return st;
     a.rf = rf;
     a.out = out;
+    const SplitPlan sp = plan_split(tp, acq);
+    const size_t need = split_ws_bytes(sp, acq, grid);
+    if (need > 0 && workspace && ws_bytes >= need) {
+        if (((uintptr_t)workspace & 3) != 0)
+            return fail(WF_ERR_INVALID_ARG, "workspace is not 4-byte aligned");
+        if (overlaps(workspace, need, out, out_bytes) ||
+            overlaps(workspace, need, rf, rf_bytes_of(acq)))
+            return fail(WF_ERR_INVALID_ARG, "workspace overlaps rf or out");
+        a.partial = static_cast<float*>(workspace);
+        a.nsplit = sp.nsplit;
+        a.split_chunks = sp.chunks;
+    }
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
                                             groups_of(a, tp), a, tp.lds, (hipStream_t)stream)
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
                                                  groups_of(a, tp), a, tp.lds, (hipStream_t)stream);
+    if (e == hipSuccess && a.partial)
+        e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "DAS kernel launch" : "dy/dc kernel launch");
     return ok();
 }
@@ -459,22 +506,45 @@ int32_t wf_abi_version(void) { return WF_ABI_VERSION; }
 const char* wf_last_error(void) { return g_err.c_str(); }
 
 wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
-                      const int32_t* tx_elem, const wf_grid* grid, float* out, void* stream) {
-    return das_common(0, 0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, stream);
+                      const int32_t* tx_elem, const wf_grid* grid, float* out, void* workspace,
+                      uint64_t workspace_bytes, void* stream) {
+    return das_common(0, 0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, workspace,
+                      workspace_bytes, stream);
 }
 
 wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid, float* out,
-                     void* stream) {
-    return das_common(1, 0, rf, probe, acq, nullptr, angles_rad, tref, grid, out, stream);
+                     void* workspace, uint64_t workspace_bytes, void* stream) {
+    return das_common(1, 0, rf, probe, acq, nullptr, angles_rad, tref, grid, out, workspace,
+                      workspace_bytes, stream);
 }
 
 wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                      const wf_grid* grid, float* dydc, void* stream) {
+                      const wf_grid* grid, float* dydc, void* workspace,
+                      uint64_t workspace_bytes, void* stream) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
     return das_common(mode, 1, rf, probe, acq, mode == 0 ? tx_elem : nullptr,
-                      mode == 1 ? angles_rad : nullptr, tref, grid, dydc, stream);
+                      mode == 1 ? angles_rad : nullptr, tref, grid, dydc, workspace,
+                      workspace_bytes, stream);
+}
+
+wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* acq,
+                           const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                           const wf_grid* grid, uint64_t* bytes) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
+    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    if (st != WF_OK) return st;
+    Geometry g;
+    build_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                   mode == 1 ? angles_rad : nullptr, tref, grid, &g);
+    TilePlan tp;
+    if (!choose_tile(g, acq, grid, &tp))
+        return fail(WF_ERR_UNSUPPORTED, "pixel spacing too coarse for the DAS tile window");
+    *bytes = split_ws_bytes(plan_split(tp, acq), acq, grid);
+    return ok();
 }
 
 // Workspace of the two-stage adjoint for one frame: every (transmit,

@@ -82,7 +82,11 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame * a.T * a.C * a.S;
     const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * NT)
 
-    for (int c0 = 0; c0 < a.C; c0 += kChunk) {
+    // channel split: this workgroup sums channel chunks [cb, ce)
+    const int split = blockIdx.z;
+    const int cb = split * a.split_chunks * kChunk;
+    const int ce = min(a.C, cb + a.split_chunks * kChunk);
+    for (int c0 = cb; c0 < ce; c0 += kChunk) {
         __syncthreads();  // previous chunk's readers of b_tab / windows are done
         chunk_tables(a, g, c0, b_tab);
         __syncthreads();
@@ -234,9 +238,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     }
 
     const float scale = (OP == kOpValue) ? 1.0f : a.neg_inv_c;
+    float* dst = a.partial ? a.partial + (size_t)split * a.F * a.nz * a.nx : a.out;
 #pragma unroll
     for (int k = 0; k < PX; ++k)
-        if (p.valid[k]) a.out[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] = acc[k] * scale;
+        if (p.valid[k]) dst[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] = acc[k] * scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -284,7 +289,7 @@ template <int MODE, typename RT, int NT, int PX, int NG, int OP>
 hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP>, lds);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F);
+    dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
     hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP>), grid, dim3(NT), lds, s, a);
     return hipGetLastError();
 }
@@ -313,11 +318,32 @@ hipError_t launch_mode(int dtype, int nt, int px, int groups, const DasArgs& a, 
     }
 }
 
+// Sum of the channel-split partial frames, in split order (deterministic).
+__global__ void __launch_bounds__(256)
+    split_reduce_kernel(const float* __restrict__ partial, int nsplit, size_t n,
+                        float* __restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        float v = partial[i];
+        for (int k = 1; k < nsplit; ++k) v += partial[(size_t)k * n + i];
+        out[i] = v;
+    }
+}
+
 }  // namespace
+
 
 static bool shape_ok(int nt, int px, int groups) {
     if (nt == 1024 || nt == 512) return px == 2 && groups <= 2;
     return nt == 256 && (px == 4 || px == 1) && groups <= kMaxGroups;
+}
+
+hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
+                               hipStream_t s) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
+                       nsplit, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,

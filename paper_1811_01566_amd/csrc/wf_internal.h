@@ -65,6 +65,9 @@ struct DasArgs {
     const ChConst* ch_tab;
     const float* g;     // adjoint: cotangent [F][nz][nx]
     float* grad;        // adjoint: d L / d rf [F][T][C][S]
+    int nsplit;         // channel split: workgroups per tile along channels (1: none)
+    int split_chunks;   // channel chunks of one split
+    float* partial;     // split partial frames [nsplit][F][nz][nx] (null: write out)
     int ntiles;         // adjoint: ntz * ntx
     float* ws_win;      // adjoint workspace: window of (t, c, tile), nst + 1 samples
     int* ws_a0;         // adjoint workspace: first sample of that window or kNoWindow
@@ -92,6 +95,8 @@ hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const Das
                       size_t lds_bytes, hipStream_t s);
 hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
                            size_t lds_bytes, hipStream_t s);
+hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
+                               hipStream_t s);
 hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
                               hipStream_t s);
 hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s);

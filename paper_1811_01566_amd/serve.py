@@ -4,7 +4,7 @@ Requests of different geometries (array size, transmit count, record length,
 pixel grid, STAI or PWI) arrive over time.  The service keeps, per shape
 class, resident executors: the geometry's constant table (cached by libwf),
 device buffers for one frame (RF in, beamformed RF, B-mode out, column
-maxima) and a captured HIP graph of the whole path (DAS -> envelope -> log
+maxima, the DAS channel-split workspace of small grids) and a captured HIP graph of the whole path (DAS -> envelope -> log
 compression), replayed per request.  Up to ``n_streams`` requests are in
 flight at once, each on its own stream, so a request that arrives while
 others run is admitted as soon as a stream slot and memory are free, and its
@@ -36,7 +36,7 @@ import time
 from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional, Sequence
 
-from . import Scan, bmode, das
+from . import Scan, bmode, das, das_workspace_bytes
 
 
 @dataclass
@@ -94,7 +94,9 @@ class Executor:
         self.y = torch.empty((1, g.nz, g.nx), dtype=torch.float32, device=device)
         self.out = torch.empty_like(self.y)
         self.col_max = torch.empty((1, g.nx), dtype=torch.float32, device=device)
-        self.nbytes = frame_bytes(req)
+        wsb = das_workspace_bytes(req.scan, req.n_s, 1)
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=device) if wsb else None
+        self.nbytes = frame_bytes(req) + wsb
         self.graph = None
         self.busy = False
         self.last_used = 0.0
@@ -115,7 +117,7 @@ class Executor:
             torch.cuda.synchronize(device)
 
     def _launch(self):
-        das(self.scan, self.rf, out=self.y)
+        das(self.scan, self.rf, out=self.y, workspace=self.ws)
         bmode(self.y, self.dr_db, out=self.out, col_max=self.col_max)
 
     def run(self):

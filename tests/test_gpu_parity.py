@@ -247,3 +247,31 @@ def test_full_size_sampled_columns(wf_gpu, name, cols):
     assert err <= NL2_TOL
     assert d <= DB_TOL
     assert bc.max() == 0.0 and bc.min() >= -w.dr_db
+
+
+@pytest.mark.parametrize("name", ["stai_small", "paper_pwi"])
+def test_das_channel_split_matches_unsplit(wf_gpu, name):
+    """Small grids share each tile's channels among several workgroups
+    (partial frames summed in split order); without a workspace the same call
+    runs unsplit.  Both agree with the oracle and with each other to FP32
+    rounding, and each is bitwise repeatable."""
+    torch = _torch()
+    w = phantom.get_workload(name)
+    scan = scan_from_workload(w)
+    need = wf_gpu.das_workspace_bytes(scan, w.n_s, 1)
+    assert need > 0  # the geometry splits
+    rf = _gpu(phantom.synth_rf(w))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    split = wf_gpu.das(scan, rf, workspace=ws)
+    split2 = wf_gpu.das(scan, rf, workspace=ws)
+    plain = wf_gpu.das(scan, rf, workspace=torch.empty(0, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(split, split2)
+    assert nl2(split.cpu().numpy(), plain.cpu().numpy()) <= 1e-6
+    cols = (0, w.nx // 2, w.nx - 1)
+    iz = np.repeat(np.arange(w.nz), len(cols)).reshape(w.nz, len(cols))
+    ix = np.tile(np.asarray(cols), (w.nz, 1))
+    ref = oracle.das_workload(phantom.synth_rf(w)[0].astype(np.float64), w, iz, ix)
+    err = nl2(split[0].cpu().numpy()[:, list(cols)], ref)
+    print(f"{name} split: nL2 {err:.2e}")
+    assert err <= NL2_TOL

@@ -143,6 +143,9 @@ class GpuBackend:
     def new_executor(self, req: Request) -> Executor:
         return Executor(req, self.device, self.use_graphs)
 
+    def executor_bytes(self, req: Request) -> int:
+        return frame_bytes(req) + das_workspace_bytes(req.scan, req.n_s, 1)
+
     def launch(self, ex: Executor, req: Request, stream):
         torch = self.torch
         with torch.cuda.stream(stream):
@@ -187,6 +190,10 @@ class Server:
         self.max_inflight = 0
 
     # -- memory ------------------------------------------------------------
+    def _bytes_of(self, req: Request) -> int:
+        size = getattr(self.backend, "executor_bytes", None)
+        return size(req) if size is not None else frame_bytes(req)
+
     def _evict_for(self, need: int) -> bool:
         idle = sorted(((ex.last_used, key, ex) for key, lst in self.executors.items()
                        for ex in lst if not ex.busy), key=lambda t: t[0])
@@ -203,7 +210,7 @@ class Server:
         for ex in self.executors[key]:
             if not ex.busy:
                 return ex
-        need = frame_bytes(req)
+        need = self._bytes_of(req)
         if need > self.budget:
             raise ValueError(f"request {req.rid} needs {need} bytes, above the HBM budget")
         if not self._evict_for(need):
@@ -214,6 +221,25 @@ class Server:
         self.executors[key].append(ex)
         self.bytes_in_use += ex.nbytes
         return ex
+
+    def prewarm(self, requests: Sequence[Request], per_class: Optional[int] = None) -> None:
+        """Build up to `per_class` executors (default: one per stream slot)
+        for every shape class in `requests`, within the HBM budget, so that
+        no executor - with its synchronising warm-up and graph capture - is
+        built while a trace is served."""
+        per_class = len(self.streams) if per_class is None else per_class
+        seen = {}
+        for r in requests:
+            seen.setdefault(class_key(r), r)
+        for key, r in seen.items():
+            while len(self.executors[key]) < per_class:
+                need = self._bytes_of(r)
+                if self.bytes_in_use + need > self.budget:
+                    return
+                ex = self.backend.new_executor(r)
+                self.executors_built += 1
+                self.executors[key].append(ex)
+                self.bytes_in_use += ex.nbytes
 
     # -- scheduling ----------------------------------------------------------
     def submit(self, req: Request) -> None:

@@ -124,3 +124,21 @@ def test_oversized_request_is_rejected():
     srv = Server(FakeBackend(clock, cost=lambda r: 1e-3), hbm_budget=1000, n_streams=2)
     with pytest.raises(ValueError, match="budget"):
         _run(srv, [Request(0, _scan(), Shape(256), 0.0)], clock)
+
+
+
+def test_prewarm_builds_per_class_within_budget():
+    clock = FakeClock()
+    be = FakeBackend(clock, cost=lambda r: 1e-3)
+    srv = Server(be, hbm_budget=1 << 30, n_streams=3)
+    # three shape classes (transmit counts 2, 4, 6)
+    reqs = [Request(i, _scan(n_tx=2 + 2 * k), Shape(256), arrival=0.0)
+            for i, k in enumerate([0, 1, 0, 2, 1])]
+    srv.prewarm(reqs)
+    assert srv.executors_built == 9  # 3 classes x 3 stream slots
+    _run(srv, reqs, clock)
+    assert srv.executors_built == 9  # serving built nothing more
+    small = Server(FakeBackend(clock, cost=lambda r: 1e-3),
+                   hbm_budget=2 * frame_bytes(reqs[0]) + 1, n_streams=3)
+    small.prewarm(reqs)
+    assert small.executors_built == 2 and small.bytes_in_use <= small.budget

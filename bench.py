@@ -250,8 +250,8 @@ def serve_main(args, wf, phantom, torch, np):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the DAS path needs no collective and this build "
-              "measures a single MI355X (--gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the DAS path needs no collective and the "
+              "benchmark measures a single MI355X (--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,6 +1,6 @@
 """HIP path vs the FP64 oracle, through the C ABI, on an MI355X.
 
-Bars (stated by the benchmark spec's tolerances of the path):
+Bars (the tolerances the path is held to):
   beamformed RF   normalised L2 error <= 1e-5 (FP32 compute, any RF dtype,
                   oracle fed the same RF values);
   B-mode          max |dB difference| <= 0.01 dB;

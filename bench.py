@@ -1,7 +1,7 @@
 """Benchmark of the DAS -> envelope -> log-compression B-mode path on one GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pwi]
-                    [--no-cpu-baseline] [--latency-frames N]
+                    [--no-cpu-baseline] [--latency-frames N] [--h2d-frames N]
 
 A step is one frame through the whole hot path - DAS (PWI or STAI), the FFT
 analytic-signal envelope with per-column maxima, and the dB log compression
@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--rf-dtype", default="int16", choices=["int16", "float16", "float32"],
                     help="RF storage: int16 ADC counts, FP16 (counts x 2^-13) or FP32")
     ap.add_argument("--latency-frames", type=int, default=300)
+    ap.add_argument("--h2d-frames", type=int, default=20,
+                    help="frames of the PCIe-inclusive section (0 leaves it out, e.g. under a "
+                         "kernel trace, whose per-kernel averages it would mix with launches "
+                         "that overlap host copies)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=256,
                     help="image columns of the frame the CPU oracle computes")
@@ -247,6 +251,63 @@ def serve_main(args, wf, phantom, torch, np):
     print(json.dumps(res), flush=True)
 
 
+def pcie_inclusive(wf, torch, scan, w, rf, y, out, col_max, das_ws, stream, n_h2d):
+    """Frames/s with the RF streamed from pinned host memory: frame i's RF is
+    copied on a second stream into one of two device buffers while frame i-1
+    is processed.  The headline value keeps the RF resident in HBM."""
+    if n_h2d <= 0:
+        return None
+    dev = rf.device
+    # allocated pinned and filled by a device-to-host copy: no bulk memcpy on
+    # host threads right before the timed loop
+    host_rf = torch.empty(rf.shape, dtype=rf.dtype, pin_memory=True)
+    host_rf.copy_(rf)
+    copy_stream = torch.cuda.Stream(device=dev)
+    bufs = [torch.empty_like(rf) for _ in range(2)]
+    copied = [torch.cuda.Event() for _ in range(2)]
+    freed = [torch.cuda.Event() for _ in range(2)]
+    for ev in freed:
+        ev.record(stream)
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(copy_stream):
+        h0.record(copy_stream)
+        bufs[0].copy_(host_rf, non_blocking=True)
+        h1.record(copy_stream)
+    copy_stream.synchronize()
+    h2d_ms = h0.elapsed_time(h1)
+
+    def frames(n):
+        enqueue_max = 0.0
+        for i in range(n):
+            t_i = time.perf_counter()
+            b = i % 2
+            with torch.cuda.stream(copy_stream):
+                copy_stream.wait_event(freed[b])
+                bufs[b].copy_(host_rf, non_blocking=True)
+                copied[b].record(copy_stream)
+            stream.wait_event(copied[b])
+            wf.das(scan, bufs[b], out=y, workspace=das_ws)
+            freed[b].record(stream)
+            wf.bmode(y, w.dr_db, out=out, col_max=col_max)
+            enqueue_max = max(enqueue_max, time.perf_counter() - t_i)
+        torch.cuda.synchronize()
+        return enqueue_max
+
+    # untimed pass first: the runtime sets up the copy stream and grows its
+    # per-queue resources the first time the host runs many frames ahead,
+    # which blocks the enqueueing thread for several ms
+    frames(n_h2d)
+    t_h = time.perf_counter()
+    enqueue_max = frames(n_h2d)
+    fps = w.n_frames * n_h2d / (time.perf_counter() - t_h)
+    return {"frames_per_s": round(fps, 2), "h2d_ms_per_step": round(h2d_ms, 4),
+            "rf_bytes_per_step": int(rf.numel() * rf.element_size()),
+            "frames": n_h2d, "host_enqueue_ms_max": round(enqueue_max * 1e3, 3),
+            "note": "RF copied from pinned host memory on a second stream, "
+                    "double-buffered against DAS + B-mode; timed after one untimed "
+                    "pass of the same loop"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -409,39 +470,8 @@ def main():
     del grad_rf, adj_ws
 
     # ---- secondary: RF streamed from pinned host memory (PCIe-inclusive) -
-    # frame i's RF is copied on a second stream into one of two device
-    # buffers while frame i-1 is processed; the headline value keeps the RF
-    # resident in HBM
-    host_rf = rf.cpu().pin_memory()
-    copy_stream = torch.cuda.Stream(device=dev)
-    bufs = [torch.empty_like(rf) for _ in range(2)]
-    copied = [torch.cuda.Event() for _ in range(2)]
-    freed = [torch.cuda.Event() for _ in range(2)]
-    n_h2d = 20
-    for ev in freed:
-        ev.record(stream)
-    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(copy_stream):
-        h0.record(copy_stream)
-        bufs[0].copy_(host_rf, non_blocking=True)
-        h1.record(copy_stream)
-    copy_stream.synchronize()
-    h2d_ms = h0.elapsed_time(h1)
-    torch.cuda.synchronize()
-    t_h = time.perf_counter()
-    for i in range(n_h2d):
-        b = i % 2
-        with torch.cuda.stream(copy_stream):
-            copy_stream.wait_event(freed[b])
-            bufs[b].copy_(host_rf, non_blocking=True)
-            copied[b].record(copy_stream)
-        stream.wait_event(copied[b])
-        wf.das(scan, bufs[b], out=y, workspace=das_ws)
-        freed[b].record(stream)
-        wf.bmode(y, w.dr_db, out=out, col_max=col_max)
-    torch.cuda.synchronize()
-    pcie_fps = F * n_h2d / (time.perf_counter() - t_h)
-    del bufs, host_rf
+    pcie = pcie_inclusive(wf, torch, scan, w, rf, y, out, col_max, das_ws, stream,
+                          args.h2d_frames)
 
     # ---- closed-loop frame latency: enqueue -> completion, one in flight --
     lat = []
@@ -501,10 +531,7 @@ def main():
         },
         "prefilter_and_qus": prefilter,
         "derivatives": derivatives,
-        "pcie_inclusive": {"frames_per_s": round(pcie_fps, 2), "h2d_ms_per_step": round(h2d_ms, 4),
-                           "rf_bytes_per_step": int(rf.numel() * rf.element_size()),
-                           "note": "RF copied from pinned host memory on a second stream, "
-                                   "double-buffered against DAS + B-mode"},
+        "pcie_inclusive": pcie,
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:

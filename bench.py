@@ -50,14 +50,14 @@ PAPER_CONTEXT = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="pwi", choices=["pwi", "stai_full", "stai_small",
                                                           "pwi_batch8", "paper_stai",
                                                           "paper_pwi"])
     ap.add_argument("--rf-dtype", default="int16", choices=["int16", "float16", "float32"],
                     help="RF storage: int16 ADC counts, FP16 (counts x 2^-13) or FP32")
-    ap.add_argument("--latency-frames", type=int, default=300)
+    ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--h2d-frames", type=int, default=20,
                     help="frames of the PCIe-inclusive section (0 leaves it out, e.g. under a "
                          "kernel trace, whose per-kernel averages it would mix with launches "
@@ -156,6 +156,17 @@ def scan_of(wf, w):
     return wf.Scan(**kw)
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, rf, ncols):
     """The FP64 oracle on `ncols` whole columns of one frame (DAS, envelope,
     log compression), scaled to frames/s."""
@@ -181,6 +192,7 @@ def cpu_baseline(w, rf, ncols):
                   f"{dt:.1f} s measured, scaled by {w.nx}/{ncols}",
         "s_per_frame": s_per_frame,
         "host_cpus": len(os.sched_getaffinity(0)),
+        "host_cpu_model": host_cpu_model(),
     }
 
 
@@ -524,6 +536,7 @@ def main():
             "peak": round(PEAK_LANE_OPS / 1e12, 2),
             "unit": "Tops/s (vector lane-ops)",
             "frac": round(achieved / PEAK_LANE_OPS, 4),
+            "frac_vs_packed_peak": round(achieved / (2 * PEAK_LANE_OPS), 4),
             "traffic": profiled_traffic(w.name),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "ops_per_launch": OPS_PER_CONTRIB * act_frac * nominal,

@@ -110,65 +110,70 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             return t;
         };
 
-        // global -> registers for pass t (nothing written yet)
+        // this lane's staged groups in the chunk: group w = tid + gi NT is
+        // channel j = w mod 16, samples [8 gg, 8 gg + 8) of its window.  A
+        // group of a channel beyond C gets a base that puts it outside every
+        // record, so the unsigned range test below covers it too.
+        int gb[NG];        // b_j + 8 gg: s0 = (a_t + gb) & ~7
+        uint32_t roff[NG]; // element offset of the channel's record in a transmit
+        uint32_t dofs[NG]; // byte offset of the group inside an LDS buffer
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            const int w = tid + gi * NT;
+            const int j = w & (kChunk - 1);
+            const int gg = w >> kChunkLog2;
+            const int c = c0 + j;
+            gb[gi] = (c < a.C) ? b_tab[j] + 8 * gg : -0x40000000;
+            roff[gi] = (uint32_t)min(c, a.C - 1) * (uint32_t)a.S;
+            dofs[gi] = (uint32_t)(j * slot + 8 * gg) * (uint32_t)sizeof(float2);
+        }
+        const uint32_t rec_bytes = (uint32_t)a.C * (uint32_t)a.S * (uint32_t)sizeof(RT);
+        constexpr int kElemLog2 = sizeof(RT) == 2 ? 1 : 2;
+
+        // global -> registers for pass t (nothing written yet); a group
+        // outside the record reads zeros through the buffer range check
         RawGroup<RT> raw[NG];
         auto issue = [&](int t) {
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
-            const RT* rf_t = rf_frame + (size_t)t * a.C * a.S;
+            const __amdgpu_buffer_rsrc_t rsrc = rf_rsrc(rf_frame + (size_t)t * a.C * a.S, rec_bytes);
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
                 if (w < ngroups) {
-                    const int j = w & (kChunk - 1);
-                    const int gg = w >> kChunkLog2;
-                    const int c = c0 + j;
-                    const int s0 = ((at + b_tab[j]) & ~7) + 8 * gg;
-                    if (c < a.C && s0 >= 0 && s0 + 8 <= a.S)
-                        raw[gi].load(rf_t + (size_t)c * a.S + s0, s0 + 8 <= a.S - 1);
-                    else
-                        raw[gi].zero();
+                    const int s0 = (at + gb[gi]) & ~7;
+                    const bool ok = (uint32_t)s0 <= (uint32_t)(a.S - 8);
+                    raw[gi].load(rsrc, ok ? (roff[gi] + (uint32_t)s0) << kElemLog2 : kOffNone);
                 }
             }
         };
-        // registers -> interpolation pairs in LDS buffer `buf`
+        // registers -> interpolation pairs in LDS buffer `buf`.  S % 8 == 0,
+        // so a group lies wholly inside or outside its record; inside, only
+        // the last pair of the record (n = S - 1, no successor) is dropped.
         auto commit = [&](int t, int buf) {
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
                 if (w < ngroups) {
-                    const int j = w & (kChunk - 1);
-                    const int gg = w >> kChunkLog2;
-                    const int c = c0 + j;
-                    const int s0 = ((at + b_tab[j]) & ~7) + 8 * gg;
+                    const int s0 = (at + gb[gi]) & ~7;
                     float v[9];
                     raw[gi].get(v);
-                    float4* dst =
-                        reinterpret_cast<float4*>(win + (buf * kChunk + j) * slot + 8 * gg);
-                    if (c < a.C && s0 >= 0 && s0 + 8 <= a.S - 1) {
-                        // whole group inside the record: every pair is valid
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            dst[i] = make_float4(fmaf(2.0f, v[2 * i], -v[2 * i + 1]),
-                                                 v[2 * i + 1] - v[2 * i],
-                                                 fmaf(2.0f, v[2 * i + 1], -v[2 * i + 2]),
-                                                 v[2 * i + 2] - v[2 * i + 1]);
-                    } else {
-                        // record edge or outside: pairs with n < 0 or n > S-2 are 0
-                        const bool inr = (c < a.C) && (s0 >= 0) && (s0 + 8 <= a.S);
+                    for (int m = 0; m < 9; ++m) opaque(v[m]);
+                    float4 o[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            float e[2], d[2];
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const int m = 2 * i + h;
-                                const bool ok = inr && (s0 + m <= a.S - 2);
-                                e[h] = ok ? fmaf(2.0f, v[m], -v[m + 1]) : 0.0f;
-                                d[h] = ok ? (v[m + 1] - v[m]) : 0.0f;
-                            }
-                            dst[i] = make_float4(e[0], d[0], e[1], d[1]);
-                        }
+                    for (int i = 0; i < 4; ++i)
+                        o[i] = make_float4(fmaf(2.0f, v[2 * i], -v[2 * i + 1]),
+                                           v[2 * i + 1] - v[2 * i],
+                                           fmaf(2.0f, v[2 * i + 1], -v[2 * i + 2]),
+                                           v[2 * i + 2] - v[2 * i + 1]);
+                    if (s0 == a.S - 8) {
+                        o[3].z = 0.0f;
+                        o[3].w = 0.0f;
                     }
+                    float4* dst = reinterpret_cast<float4*>(smem + buf * buf_bytes + dofs[gi]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) dst[i] = o[i];
                 }
             }
         };

@@ -67,6 +67,11 @@ __device__ __forceinline__ uint32_t dist_q_grid(float dxh, float dxl, ff z2, flo
 
 typedef float v2f __attribute__((ext_vector_type(2)));
 
+// Hides where a value came from: the difference of two converted int16
+// samples then stays one float subtract, where the optimiser would rewrite
+// it as an integer subtract plus a second convert.
+__device__ __forceinline__ void opaque(float& x) { asm("" : "+v"(x)); }
+
 // Byte address of window entry (u >> 23) at byte offset `off`: one shift
 // and one shift-add (the compiler would otherwise emit shift, mask, add).
 __device__ __forceinline__ uint32_t entry_addr(uint32_t u, uint32_t off) {
@@ -87,22 +92,33 @@ __device__ __forceinline__ float rect_min_dist(float xe, float xlo, float xhi, f
 }
 
 // Raw RF of one staged group (8 samples + the next one), held in registers
-// between the global load and the LDS commit so that the load latency hides
-// behind the previous transmit's arithmetic.
+// between the load and the LDS commit so that the load latency hides behind
+// the previous transmit's arithmetic.  Loads go through a raw buffer
+// resource spanning one transmit's records: a byte offset at or beyond its
+// size (kOffNone) returns zeros, so groups outside the record need neither a
+// branch nor a zero fill.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+constexpr uint32_t kOffNone = 0x80000000u;  // beyond any record buffer (< 2 GiB)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rf_rsrc(const void* base, uint32_t bytes) {
+    // raw buffer (stride 0), 32-bit data format: out-of-range dwords read 0
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
 template <typename RT>
 struct RawGroup;
 
 template <>
 struct RawGroup<int16_t> {
-    int4 q;
+    v4u q;
     int nx;
-    __device__ __forceinline__ void load(const int16_t* p, bool next) {
-        q = *reinterpret_cast<const int4*>(p);
-        nx = next ? (int)p[8] : 0;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        nx = (int)(short)__builtin_amdgcn_raw_buffer_load_b16(r, off + 16u, 0, 0);
     }
-    __device__ __forceinline__ void zero() { q = make_int4(0, 0, 0, 0); nx = 0; }
     __device__ __forceinline__ void get(float v[9]) const {
-        const int w[4] = {q.x, q.y, q.z, q.w};
+        const int w[4] = {(int)q.x, (int)q.y, (int)q.z, (int)q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             v[2 * i] = (float)((w[i] << 16) >> 16);
@@ -114,45 +130,43 @@ struct RawGroup<int16_t> {
 
 template <>
 struct RawGroup<__half> {
-    int4 q;
-    float nx;
-    __device__ __forceinline__ void load(const __half* p, bool next) {
-        q = *reinterpret_cast<const int4*>(p);
-        nx = next ? __half2float(p[8]) : 0.0f;
+    v4u q;
+    unsigned nx;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        nx = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, off + 16u, 0, 0);
     }
-    __device__ __forceinline__ void zero() { q = make_int4(0, 0, 0, 0); nx = 0.0f; }
     __device__ __forceinline__ void get(float v[9]) const {
-        const int w[4] = {q.x, q.y, q.z, q.w};
+        const unsigned w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             __half_raw lo, hi;
-            lo.x = (unsigned short)(w[i] & 0xFFFF);
-            hi.x = (unsigned short)((unsigned)w[i] >> 16);
+            lo.x = (unsigned short)(w[i] & 0xFFFFu);
+            hi.x = (unsigned short)(w[i] >> 16);
             v[2 * i] = __half2float(__half(lo));
             v[2 * i + 1] = __half2float(__half(hi));
         }
-        v[8] = nx;
+        __half_raw n;
+        n.x = (unsigned short)(nx & 0xFFFFu);
+        v[8] = __half2float(__half(n));
     }
 };
 
 template <>
 struct RawGroup<float> {
-    float4 a, b;
-    float nx;
-    __device__ __forceinline__ void load(const float* p, bool next) {
-        a = *reinterpret_cast<const float4*>(p);
-        b = *reinterpret_cast<const float4*>(p + 4);
-        nx = next ? p[8] : 0.0f;
-    }
-    __device__ __forceinline__ void zero() {
-        a = make_float4(0, 0, 0, 0);
-        b = a;
-        nx = 0.0f;
+    v4u a, b;
+    unsigned nx;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+        nx = __builtin_amdgcn_raw_buffer_load_b32(r, off + 32u, 0, 0);
     }
     __device__ __forceinline__ void get(float v[9]) const {
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-        v[8] = nx;
+        v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
+        v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
+        v[4] = __uint_as_float(b.x); v[5] = __uint_as_float(b.y);
+        v[6] = __uint_as_float(b.z); v[7] = __uint_as_float(b.w);
+        v[8] = __uint_as_float(nx);
     }
 };
 

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 3
+#define WF_ABI_VERSION 4
 
 typedef enum {
     WF_OK = 0,
@@ -250,11 +250,15 @@ wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* st
 
 /*
  * Launch plan the DAS calls would use for this geometry (host only; touches
- * no device).  info (HOST int32[11]) receives: pixels per lane, tile depth,
+ * no device).  info (HOST int32[16]) receives: pixels per lane, tile depth,
  * tile width, window-local delay clamp (samples), staged window entries,
  * LDS entries per window, LDS bytes per workgroup, tiles along z, tiles
- * along x, channels per pass, threads per workgroup.  mode 0 = STAI, 1 = PWI.  Returns
- * WF_ERR_UNSUPPORTED when no tile shape fits (as the DAS calls would).
+ * along x, channels per pass, threads per workgroup, then the work split
+ * used when the caller passes wf_das_workspace's bytes: items per tile,
+ * channel chunks per item, transmit splits, transmits per item, and the
+ * workgroups launched per frame (items that run no pass are left out).
+ * mode 0 = STAI, 1 = PWI.  Returns WF_ERR_UNSUPPORTED when no tile shape
+ * fits (as the DAS calls would).
  */
 wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                            const int32_t* tx_elem, const double* angles_rad, int32_t tref,

@@ -228,7 +228,8 @@ def das_pwi(rf, scan: Scan, out=None, workspace=None, stream=None):
 
 
 TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
-                    "chunk", "threads")
+                    "chunk", "threads", "nsplit", "split_chunks", "split_tx_parts",
+                    "split_tx", "workgroups")
 
 
 def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:
@@ -240,7 +241,7 @@ def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:
     tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
     ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
     tref = _tref(scan) if mode == 1 else 0
-    info = (ctypes.c_int32 * 11)()
+    info = (ctypes.c_int32 * len(TILE_INFO_FIELDS))()
     _lib.check(lib.wf_das_tile_info(mode, probe, acq, tx, ang, tref, grid,
                                     ctypes.cast(info, _lib.c_int32_p)), "wf_das_tile_info")
     return dict(zip(TILE_INFO_FIELDS, list(info)))

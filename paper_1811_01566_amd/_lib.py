@@ -13,7 +13,7 @@ WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
 WF_ERR_WORKSPACE = -4
-WF_ABI_VERSION = 3
+WF_ABI_VERSION = 4
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2
 WF_PWI_TREF_FIRST, WF_PWI_TREF_CENTRE = 0, 1

@@ -2,12 +2,15 @@
 // tables, tile selection and stream-ordered kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -353,7 +356,7 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 // Validates a DAS-shaped call and fills the kernel arguments and plan.
 wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
                       const double* angles, int32_t tref, const wf_grid* grid, wf::DasArgs* a,
-                      TilePlan* tp) {
+                      TilePlan* tp, Geometry* gout = nullptr) {
     wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
     Geometry g;
@@ -379,6 +382,8 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->xcd_order = (WF_DAS_XCD_ORDER && (tp->ntz * tp->ntx) % 8 == 0) ? 1 : 0;
     a->nsplit = 1;  // no channel split unless the caller's workspace allows one
     a->split_chunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
+    a->nts = 1;
+    a->split_tx = acq->n_tx;
     a->partial = nullptr;
     a->ng = tp->nst / 8;
     a->nst = tp->nst;
@@ -398,6 +403,7 @@ wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const 
     a->neg_inv_c = (float)(-1.0 / acq->c);
     a->tx_tab = ce.tx;
     a->ch_tab = ce.ch;
+    if (gout) *gout = std::move(g);
     return WF_OK;
 }
 
@@ -423,23 +429,276 @@ int groups_of(const wf::DasArgs& a, const TilePlan& tp) {
 // number of frames), so a batch gives the same bits as its frames one by
 // one.  The target is the number of workgroups the GPU holds at once
 // (256 CUs x the workgroups of this shape one CU holds).
+// ---------------------------------------------------------------------------
+// Work split of the gather: (tile, chunk range, transmit range) items
+// ---------------------------------------------------------------------------
+
 struct SplitPlan {
-    int nsplit = 1, chunks = 1;
+    int nsplit = 1;  // items per tile = chunk splits x nts
+    int chunks = 1;  // channel chunks of one split
+    int nts = 1;     // transmit splits
+    int txs = 1;     // transmits of one split
+    // work list: the items that run any pass (code tile * nsplit + split),
+    // heaviest first; empty for grids left to the plain grid order
+    std::vector<int> order;
+    std::string key;  // geometry key of the plan (device copies of `order`)
 };
 
-SplitPlan plan_split(const TilePlan& tp, const wf_acq* acq) {
-    SplitPlan sp;
-    const int nchunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
-    sp.chunks = nchunks;
+// Transmit passes the gather runs for each (tile, channel chunk, transmit),
+// by the kernel's own tests evaluated in float on the host: a chunk runs if
+// the receive aperture of one of its channels reaches the tile, a pass if
+// the transmit's windows reach into the record.  A window base may differ
+// from the device's by one sample at a rounding tie; the map only steers
+// the split, never what is computed.  pre[(tile * nch + chunk) * (T + 1) + t]
+// counts the passes of transmits [0, t).
+void pass_map(int mode, const Geometry& g, const wf_acq* acq, const wf_grid* grid,
+              const TilePlan& tp, std::vector<uint16_t>* pre) {
+    const int T = acq->n_tx, C = acq->n_ch, S = acq->n_s;
+    const int nch = (C + wf::kChunk - 1) / wf::kChunk;
+    const int tiles = tp.ntz * tp.ntx;
+    const int TZ = 1 << tp.tz_log2;
+    const int TXW = (tp.threads * tp.px) >> tp.tz_log2;
+    pre->assign((size_t)tiles * nch * (T + 1), 0);
+    std::vector<int> at(T), b(C);
+    std::vector<char> act(C);
+    auto rmd = [](float xe, float xlo, float xhi, float zlo, float zhi) {
+        const float dx = std::max(0.0f, std::max(xlo - xe, xe - xhi));
+        const float dz = std::min(std::max(0.0f, zlo), zhi);
+        return std::sqrt(dx * dx + dz * dz);
+    };
+    for (int tile = 0; tile < tiles; ++tile) {
+        const int iz0 = (tile % tp.ntz) * TZ, ix0 = (tile / tp.ntz) * TXW;
+        const int iz1 = std::min(iz0 + TZ, grid->nz) - 1;
+        const int ix1 = std::min(ix0 + TXW, grid->nx) - 1;
+        const float za = g.Z0.x + (float)iz0 * g.dZ.x, zb = g.Z0.x + (float)iz1 * g.dZ.x;
+        const float xa = g.x0f + (float)ix0 * g.dxf, xb = g.x0f + (float)ix1 * g.dxf;
+        const float zlo = std::min(za, zb), zhi = std::max(za, zb);
+        const float xlo = std::min(xa, xb), xhi = std::max(xa, xb);
+        for (int t = 0; t < T; ++t) {
+            const wf::TxConst& tc = g.tx[t];
+            if (mode == 1) {
+                const float c0 = tc.v0.x, az = tc.v0.z, ax = tc.v1.x;
+                const float m00 = c0 + (float)iz0 * az + (float)ix0 * ax;
+                const float m10 = c0 + (float)iz1 * az + (float)ix0 * ax;
+                const float m01 = c0 + (float)iz0 * az + (float)ix1 * ax;
+                const float m11 = c0 + (float)iz1 * az + (float)ix1 * ax;
+                at[t] = (int)std::floor(std::min(std::min(m00, m10), std::min(m01, m11))) - 1;
+            } else {
+                at[t] = (int)std::floor(rmd(tc.v0.z, xlo, xhi, zlo, zhi) + g.O.x) - 1;
+            }
+        }
+        for (int c = 0; c < C; ++c) {
+            const float xe = g.ch[c].z;
+            b[c] = (int)std::floor(rmd(xe, xlo, xhi, zlo, zhi)) - 1;
+            const float dxm = std::max(0.0f, std::max(xlo - xe, xe - xhi));
+            act[c] = !(g.fnum2 > 0.0f) || (g.fnum2 * dxm <= zhi + 1.0f);
+        }
+        for (int k = 0; k < nch; ++k) {
+            int bmin = INT_MAX, bmax = INT_MIN;
+            bool any = false;
+            for (int j = 0; j < wf::kChunk; ++j) {
+                const int c = k * wf::kChunk + j;
+                const int bj = c < C ? b[c] : 0;  // the kernel's table holds 0 there
+                bmin = std::min(bmin, bj);
+                bmax = std::max(bmax, bj);
+                any = any || (c < C && act[c]);
+            }
+            if (!any) continue;
+            uint16_t* r = pre->data() + ((size_t)tile * nch + k) * (T + 1);
+            for (int t = 0; t < T; ++t)
+                r[t + 1] = (uint16_t)(r[t] + !(at[t] + bmin > S - 2 || at[t] + bmax + tp.nst < 0));
+        }
+    }
+}
+
+// Estimated passes of every item of a plan (an item that runs nothing: 0):
+// its passes, the receive delays of each chunk it runs (about 5.5 passes)
+// and a fixed ~2 us (launch, tables, pixel set, scans over transmits that
+// do not reach the tile), which is many passes of a small tile.
+std::vector<double> item_costs(const SplitPlan& sp, const std::vector<uint16_t>& pre, int tiles,
+                               int nch, int T, double pass_s) {
+    const double fixed = std::max(1.0, 2e-6 / pass_s);
+    const int nsc = sp.nsplit / sp.nts;
+    std::vector<double> cost((size_t)tiles * sp.nsplit, 0.0);
+    for (int tile = 0; tile < tiles; ++tile)
+        for (int sc = 0; sc < nsc; ++sc)
+            for (int st = 0; st < sp.nts; ++st) {
+                long passes = 0;
+                int chunks_run = 0;
+                const int k1 = std::min(nch, (sc + 1) * sp.chunks);
+                const int t0 = st * sp.txs, t1 = std::min(T, t0 + sp.txs);
+                for (int k = sc * sp.chunks; k < k1; ++k) {
+                    const uint16_t* r = pre.data() + ((size_t)tile * nch + k) * (T + 1);
+                    const int n = r[t1] - r[t0];
+                    passes += n;
+                    chunks_run += n > 0;
+                }
+                if (passes > 0)
+                    cost[(size_t)tile * sp.nsplit + sc * sp.nts + st] =
+                        passes + 5.5 * chunks_run + fixed;
+            }
+    return cost;
+}
+
+// The non-empty items, heaviest first (ties by code: deterministic).
+std::vector<int> item_order(const std::vector<double>& cost) {
+    std::vector<int> order;
+    for (size_t i = 0; i < cost.size(); ++i)
+        if (cost[i] > 0.0) order.push_back((int)i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return cost[x] > cost[y]; });
+    return order;
+}
+
+// Time of a plan in passes of one workgroup.  Workgroups are handed out in
+// order, round-robin over the 8 XCDs, each to a free slot of its XCD (32
+// CUs x `occ` co-resident workgroups, each running at 1/occ of a CU); a
+// workgroup whose XCD is full holds back the ones behind it.  Items that
+// run nothing are not launched: their outputs are cleared first (one
+// output-sized write per split), and a split adds the reduce kernel
+// (nsplit + 1 frame-sized streams) - both at ~4 TB/s, plus launches.
+double plan_time(const SplitPlan& sp, const std::vector<double>& cost,
+                 const std::vector<int>& order, int occ, double pass_s, double frame_bytes) {
+    using MinQ = std::priority_queue<double, std::vector<double>, std::greater<double>>;
+    std::vector<MinQ> xcd(8);
+    for (auto& q : xcd)
+        for (int i = 0; i < 32 * occ; ++i) q.push(0.0);
+    double clock = 0.0, end = 0.0;
+    for (size_t i = 0; i < order.size(); ++i) {
+        MinQ& q = xcd[i & 7];
+        const double start = std::max(clock, q.top());
+        q.pop();
+        const double fin = start + cost[order[i]] * occ;
+        q.push(fin);
+        clock = start;
+        end = std::max(end, fin);
+    }
+    double extra = 0.0;
+    if (order.size() < cost.size()) extra += sp.nsplit * frame_bytes / 4e12 + 2e-6;
+    if (sp.nsplit > 1) extra += (sp.nsplit + 1) * frame_bytes / 4e12 + 3e-6;
+    return end + extra / pass_s;
+}
+
+std::mutex g_split_mu;
+std::map<std::string, SplitPlan> g_split_cache;
+
+// The split of a geometry: the candidate (chunks per split x transmit
+// splits of 1, 2 or 4) with the least plan_time.  It depends on the
+// geometry and the tile plan only, never on the frame count, so a batch and
+// its frames one by one run the same items.  Grids with many tiles per
+// slot are balanced by the dispatcher already and are not split.
+SplitPlan plan_split(int mode, const Geometry& g, const wf_acq* acq, const wf_grid* grid,
+                     const TilePlan& tp) {
+    SplitPlan base;
+    const int T = acq->n_tx;
+    const int nch = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
+    base.chunks = nch;
+    base.txs = T;
     const long long tiles = (long long)tp.ntz * tp.ntx;
     const int by_waves = std::max(1, 16 / (tp.threads / 64));
     const int by_lds = std::max(1, (int)(kLdsHard / std::max<size_t>(tp.lds, 1)));
-    const long long target = 256LL * std::min(by_waves, by_lds);
-    if (tiles >= target || nchunks < 2) return sp;
-    const int want = (int)std::min<long long>(nchunks, (target + tiles - 1) / tiles);
-    sp.chunks = (nchunks + want - 1) / want;
-    sp.nsplit = (nchunks + sp.chunks - 1) / sp.chunks;
-    return sp;
+    const int occ = std::min(by_waves, by_lds);
+    if (tiles >= 8LL * 256 * occ) return base;
+
+    std::string key;
+    key_add(key, &mode, sizeof mode);
+    const int dims[] = {acq->n_tx, acq->n_ch, acq->n_s, grid->nz, grid->nx, tp.threads, tp.px,
+                        tp.tz_log2, tp.nst, (int)tp.lds};
+    key_add(key, dims, sizeof dims);
+    const float geo[] = {g.Z0.x, g.dZ.x, g.x0f, g.dxf, g.fnum2, g.O.x};
+    key_add(key, geo, sizeof geo);
+    key_add(key, g.tx.data(), g.tx.size() * sizeof(wf::TxConst));
+    key_add(key, g.ch.data(), g.ch.size() * sizeof(wf::ChConst));
+    {
+        std::lock_guard<std::mutex> lk(g_split_mu);
+        auto it = g_split_cache.find(key);
+        if (it != g_split_cache.end()) return it->second;
+    }
+
+    std::vector<uint16_t> pre;
+    pass_map(mode, g, acq, grid, tp, &pre);
+    // one pass: NT x PX pixels x 16 channels at ~8 lane-ops each on one CU,
+    // and no less than ~0.5 us (barrier and LDS round trips bound small tiles)
+    const double pass_s =
+        std::max(0.5e-6, (double)tp.threads * tp.px * wf::kChunk * 8.0 / 153.6e9);
+    const double frame_bytes = (double)grid->nz * grid->nx * 4.0;
+    auto evaluate = [&](SplitPlan& sp) {
+        const std::vector<double> cost = item_costs(sp, pre, (int)tiles, nch, T, pass_s);
+        sp.order = item_order(cost);
+        return plan_time(sp, cost, sp.order, occ, pass_s, frame_bytes);
+    };
+    // candidates: no split, then chunk splits x transmit splits of 1, 2, 4
+    std::vector<std::pair<SplitPlan, double>> cand;
+    SplitPlan none = base;
+    const double none_time = evaluate(none);
+    cand.emplace_back(std::move(none), none_time);
+    for (int nsc = 1; nsc <= nch; ++nsc) {
+        const int cps = (nch + nsc - 1) / nsc;  // even chunk ranges
+        if ((nch + cps - 1) / cps != nsc) continue;  // not reachable with even ranges
+        for (int nts : {1, 2, 4}) {
+            if (nts > 1 && T / nts < 8) continue;
+            SplitPlan sp;
+            sp.chunks = cps;
+            sp.nts = nts;
+            sp.txs = (T + nts - 1) / nts;
+            sp.nsplit = nsc * nts;
+            if (sp.nsplit == 1 || sp.nsplit > 64) continue;
+            const double t = evaluate(sp);
+            cand.emplace_back(std::move(sp), t);
+        }
+    }
+    // The modelled times are coarse (pass costs vary, the dispatcher is
+    // modelled only roughly): no split unless it costs 3 % more than the
+    // best candidate; otherwise, among the candidates within 5 % of the
+    // best, the one with the most items, whose heaviest-first list then
+    // balances best (measured: finer lists win where the estimate says tie).
+    double tmin = none_time;
+    for (const auto& c : cand) tmin = std::min(tmin, c.second);
+    SplitPlan best = cand[0].first;
+    if (none_time > 1.03 * tmin) {
+        size_t most = 0;
+        for (const auto& c : cand)
+            if (c.second <= 1.05 * tmin && c.first.order.size() > most) {
+                most = c.first.order.size();
+                best = c.first;
+            }
+    }
+    best.key = key;
+    std::lock_guard<std::mutex> lk(g_split_mu);
+    g_split_cache.emplace(key, best);
+    return best;
+}
+
+// Device copy of a plan's work list on the current device (cached with
+// the geometry tables; freed by wf_geometry_cache_clear).
+std::map<std::string, int*> g_items_cache;
+
+wf_status device_items(const SplitPlan& sp, const int** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::string key = sp.key;
+    key_add(key, &dev, sizeof dev);
+    const int shape[] = {sp.nsplit, sp.chunks, sp.nts, sp.txs};
+    key_add(key, shape, sizeof shape);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_items_cache.find(key);
+    if (it != g_items_cache.end()) {
+        *out = it->second;
+        return WF_OK;
+    }
+    int* mem = nullptr;
+    const size_t bytes = sp.order.size() * sizeof(int);
+    e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
+    e = hipMemcpy(mem, sp.order.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "hipMemcpy(work list)");
+    }
+    g_items_cache.emplace(key, mem);
+    *out = mem;
+    return WF_OK;
 }
 
 size_t split_ws_bytes(const SplitPlan& sp, const wf_acq* acq, const wf_grid* grid) {
@@ -460,13 +719,15 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
         return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
     wf::DasArgs a;
     TilePlan tp;
-    if ((st = prepare_das(mode, probe, acq, tx_elem, angles, tref, grid, &a, &tp)) != WF_OK)
+    Geometry g;
+    if ((st = prepare_das(mode, probe, acq, tx_elem, angles, tref, grid, &a, &tp, &g)) != WF_OK)
         return st;
     a.rf = rf;
     a.out = out;
-    const SplitPlan sp = plan_split(tp, acq);
+    const SplitPlan sp = plan_split(mode, g, acq, grid, tp);
     const size_t need = split_ws_bytes(sp, acq, grid);
-    if (need > 0 && workspace && ws_bytes >= need) {
+    const bool split = need > 0 && workspace && ws_bytes >= need;
+    if (split) {
         if (((uintptr_t)workspace & 3) != 0)
             return fail(WF_ERR_INVALID_ARG, "workspace is not 4-byte aligned");
         if (overlaps(workspace, need, out, out_bytes) ||
@@ -475,6 +736,26 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
         a.partial = static_cast<float*>(workspace);
         a.nsplit = sp.nsplit;
         a.split_chunks = sp.chunks;
+        a.nts = sp.nts;
+        a.split_tx = sp.txs;
+    }
+    // work list: the plan's non-empty items, heaviest first, when the split
+    // it was made for is the one that runs; outputs of the items it leaves
+    // out are cleared first (a fill kernel: the call may be captured)
+    // (a grid whose every tile runs, unsplit, keeps the plain tile order)
+    const long long all_items = (long long)tp.ntz * tp.ntx * sp.nsplit;
+    const bool listed = split ? !sp.order.empty()
+                              : sp.nsplit == 1 && !sp.order.empty() &&
+                                    (long long)sp.order.size() < all_items;
+    if (listed) {
+        if ((st = device_items(sp, &a.items)) != WF_OK) return st;
+        a.nitems = (int)sp.order.size();
+        if ((long long)sp.order.size() < all_items) {
+            float* clear = split ? a.partial : out;
+            const size_t n = (split ? (size_t)sp.nsplit : 1) * (out_bytes / 4);
+            hipError_t e = wf::launch_fill(clear, n, 0.0f, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "fill launch");
+        }
     }
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
                                             groups_of(a, tp), a, tp.lds, (hipStream_t)stream)
@@ -543,7 +824,7 @@ wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* ac
     TilePlan tp;
     if (!choose_tile(g, acq, grid, &tp))
         return fail(WF_ERR_UNSUPPORTED, "pixel spacing too coarse for the DAS tile window");
-    *bytes = split_ws_bytes(plan_split(tp, acq), acq, grid);
+    *bytes = split_ws_bytes(plan_split(mode, g, acq, grid, tp), acq, grid);
     return ok();
 }
 
@@ -663,6 +944,15 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     info[8] = tp.ntx;
     info[9] = wf::kChunk;
     info[10] = tp.threads;
+    const SplitPlan sp = plan_split(mode, g, acq, grid, tp);
+    const long long all_items = (long long)tp.ntz * tp.ntx * sp.nsplit;
+    const bool listed = sp.nsplit > 1 ? !sp.order.empty()
+                                      : !sp.order.empty() && (long long)sp.order.size() < all_items;
+    info[11] = sp.nsplit;
+    info[12] = sp.chunks;
+    info[13] = sp.nts;
+    info[14] = sp.txs;
+    info[15] = (int32_t)(listed ? (long long)sp.order.size() : all_items);
     return ok();
 }
 
@@ -814,6 +1104,11 @@ wf_status wf_geometry_cache_clear(void) {
         if (e != hipSuccess && first == hipSuccess) first = e;
     }
     g_cache.clear();
+    for (auto& kv : g_items_cache) {
+        hipError_t e = hipFree(kv.second);
+        if (e != hipSuccess && first == hipSuccess) first = e;
+    }
+    g_items_cache.clear();
     if (first != hipSuccess) return hip_fail(first, "hipFree(geometry table)");
     return ok();
 }

@@ -63,7 +63,13 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
     const int frame = blockIdx.y;
-    const TileGeom g = tile_geom<NT, PX>(a, blockIdx.x);
+    // (tile, split) item of this workgroup: from the work list, or numbered
+    // tile-major in dispatch order (x fastest, then z)
+    const int item = a.items ? a.items[blockIdx.x]
+                             : (int)blockIdx.z * (int)gridDim.x + (int)blockIdx.x;
+    const int tile = item / a.nsplit;
+    const int split = item - tile * a.nsplit;
+    const TileGeom g = tile_geom<NT, PX>(a, tile);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
     // zero pad behind every window of both buffers (never overwritten)
     {
@@ -82,10 +88,12 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame * a.T * a.C * a.S;
     const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * NT)
 
-    // channel split: this workgroup sums channel chunks [cb, ce)
-    const int split = blockIdx.z;
-    const int cb = split * a.split_chunks * kChunk;
+    // split: this workgroup sums channel chunks [cb, ce) x transmits [tb, te)
+    const int ssc = split / a.nts;
+    const int cb = ssc * a.split_chunks * kChunk;
     const int ce = min(a.C, cb + a.split_chunks * kChunk);
+    const int tb = (split - ssc * a.nts) * a.split_tx;
+    const int te = min(a.T, tb + a.split_tx);
     for (int c0 = cb; c0 < ce; c0 += kChunk) {
         __syncthreads();  // previous chunk's readers of b_tab / windows are done
         chunk_tables(a, g, c0, b_tab);
@@ -103,7 +111,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
 
         // a transmit pass whose windows all lie outside the record adds nothing
         auto next_active = [&](int t) {
-            for (; t < a.T; ++t) {
+            for (; t < te; ++t) {
                 const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
                 if (!(at + bmin > a.S - 2 || at + bmax + a.nst < 0)) break;
             }
@@ -178,8 +186,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             }
         };
 
-        int t = next_active(0);
-        if (t >= a.T) continue;  // no transmit reaches this tile through this chunk
+        int t = next_active(tb);
+        if (t >= te) continue;  // no transmit reaches this tile through this chunk
 
         // software pipeline over transmit passes, two LDS buffers: commit
         // pass t into buffer `cur` (last read two passes ago, before the
@@ -190,11 +198,11 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
         int cur = 0;
-        while (t < a.T) {
+        while (t < te) {
             const int tn = next_active(t + 1);
             commit(t, cur);
             __syncthreads();
-            if (tn < a.T) issue(tn);
+            if (tn < te) issue(tn);
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
             uint32_t tq[PX];
             tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
@@ -294,7 +302,8 @@ template <int MODE, typename RT, int NT, int PX, int NG, int OP>
 hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP>, lds);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
+    const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)
+                              : dim3((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
     hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP>), grid, dim3(NT), lds, s, a);
     return hipGetLastError();
 }

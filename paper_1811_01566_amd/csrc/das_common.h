@@ -187,7 +187,7 @@ __device__ __forceinline__ TileGeom tile_geom(const DasArgs& a, int tile) {
         // workgroups are dealt to the 8 XCDs round-robin: give XCD k the
         // contiguous tile range [k n/8, (k+1) n/8) so its L2 sees a narrow
         // band of the image (and of the RF)
-        const int per = (int)gridDim.x >> 3;
+        const int per = (a.ntz * a.ntx) >> 3;
         tile = (tile & 7) * per + (tile >> 3);
     }
     const int tzi = tile % a.ntz;

@@ -65,8 +65,14 @@ struct DasArgs {
     const ChConst* ch_tab;
     const float* g;     // adjoint: cotangent [F][nz][nx]
     float* grad;        // adjoint: d L / d rf [F][T][C][S]
-    int nsplit;         // channel split: workgroups per tile along channels (1: none)
+    int nsplit;         // split: workgroups per tile (1: none) = chunk splits x nts
     int split_chunks;   // channel chunks of one split
+    int nts;            // transmit splits per chunk split (split s: chunks s / nts,
+                        // transmits s % nts)
+    int split_tx;       // transmits of one split
+    int nitems;         // workgroups along x when `items` is set
+    const int* items;   // work list: item codes tile * nsplit + split, one per workgroup
+                        // along x (null: the grid enumerates every item)
     float* partial;     // split partial frames [nsplit][F][nz][nx] (null: write out)
     int ntiles;         // adjoint: ntz * ntx
     float* ws_win;      // adjoint workspace: window of (t, c, tile), nst + 1 samples

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wf_abi_version() == 3
+    assert lib.wf_abi_version() == 4
 
 
 def _geom(n_elem=8, n_tx=4, n_ch=8, n_s=256):

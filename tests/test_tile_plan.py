@@ -55,3 +55,46 @@ def test_served_mix_shapes():
         _check(w)
         n += 1
     assert n == 207  # 23 (mode, N, T) combinations x 3 record lengths x 3 grids
+
+
+def _split(w, frames=None):
+    info = wf.tile_info(scan_from_workload(w), w.n_s, frames or w.n_frames)
+    ws = wf.das_workspace_bytes(scan_from_workload(w), w.n_s, frames or w.n_frames)
+    return info, ws
+
+
+def _check_split(w):
+    info, ws = _split(w)
+    tiles = info["ntz"] * info["ntx"]
+    nch = -(-w.n_ch // info["chunk"])  # channel chunks
+    nsc = -(-nch // info["split_chunks"])  # chunk splits
+    assert info["nsplit"] == nsc * info["split_tx_parts"]
+    assert info["split_tx"] * info["split_tx_parts"] >= w.n_tx
+    assert 0 < info["workgroups"] <= tiles * info["nsplit"]
+    # the workspace holds one partial frame per split (none without a split)
+    frame = w.nz * w.nx * 4 * w.n_frames
+    assert ws == (info["nsplit"] * frame if info["nsplit"] > 1 else 0)
+    # the plan never depends on the frame count (batch and frames agree)
+    info8, ws8 = _split(w, frames=8)
+    assert {k: v for k, v in info8.items()} == info
+    assert ws8 == (info["nsplit"] * w.nz * w.nx * 4 * 8 if info["nsplit"] > 1 else 0)
+    return info
+
+
+@pytest.mark.parametrize("name", ["stai_small", "stai_full", "pwi", "paper_stai", "paper_pwi"])
+def test_split_plans(name):
+    w = phantom.get_workload(name)
+    info = _check_split(w)
+    tiles = info["ntz"] * info["ntx"]
+    if name == "pwi":
+        # uniform work, one tile per workgroup slot: no split, every tile runs
+        assert info["nsplit"] == 1 and info["workgroups"] == tiles
+    if name == "stai_full":
+        # the 5-50 mm grid outruns the 2048-sample record and the f/1.5
+        # aperture leaves chunks idle: split, and empty items left out
+        assert info["nsplit"] > 1 and info["workgroups"] < tiles * info["nsplit"]
+
+
+def test_split_plans_served_mix():
+    for w in served_mix()[::7]:
+        _check_split(w)

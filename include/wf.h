@@ -116,12 +116,14 @@ typedef struct {
  *              not overlap rf.
  *   workspace  optional DEVICE scratch, caller-owned, 4-byte aligned, not
  *              overlapping rf or out.  When it holds at least the bytes
- *              wf_das_workspace reports (> 0 only for grids with fewer
- *              tiles than the GPU holds workgroups), the channels of each
- *              tile are shared by several workgroups whose partial frames
- *              are then summed in a fixed order; otherwise (NULL, or fewer
- *              bytes) the call runs unsplit.  Both are deterministic; they
- *              differ only in the order of the FP32 sums.
+ *              wf_das_workspace reports (> 0 for grids with too few tiles
+ *              or too uneven work per tile to balance the GPU), each tile
+ *              is split into items (channel chunks x transmit ranges) run
+ *              by separate workgroups, whose partial frames are then summed
+ *              in a fixed order; otherwise (NULL, or fewer bytes) the call
+ *              runs unsplit.  Both are deterministic; they differ only in
+ *              the order of the FP32 sums.  The split depends on the
+ *              geometry only, never on n_frames.
  * Returns WF_ERR_UNSUPPORTED when the pixel spacing is so coarse that no
  * tile shape keeps a tile's delay spread inside the kernel's window.
  */

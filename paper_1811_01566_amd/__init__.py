@@ -179,8 +179,9 @@ def _workspace_arg(scan, ns, nf, workspace, device):
 def das(scan: Scan, rf, out=None, workspace=None, stream=None):
     """Delay-and-Sum of rf [F][T][C][S] (or [T][C][S]) -> float32 [F][nz][nx]
     (or [nz][nx]).  `workspace` (uint8 device tensor of
-    :func:`das_workspace_bytes`) lets small grids split channels across
-    workgroups; it is allocated when not given."""
+    :func:`das_workspace_bytes`) lets grids with few tiles or uneven work
+    split each tile into items run by several workgroups; it is allocated
+    when not given."""
     torch = _torch()
     lib = load()
     squeeze = rf.dim() == 3

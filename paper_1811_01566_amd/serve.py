@@ -4,7 +4,7 @@ Requests of different geometries (array size, transmit count, record length,
 pixel grid, STAI or PWI) arrive over time.  The service keeps, per shape
 class, resident executors: the geometry's constant table (cached by libwf),
 device buffers for one frame (RF in, beamformed RF, B-mode out, column
-maxima, the DAS channel-split workspace of small grids) and a captured HIP graph of the whole path (DAS -> envelope -> log
+maxima, the DAS work-split workspace) and a captured HIP graph of the whole path (DAS -> envelope -> log
 compression), replayed per request.  Up to ``n_streams`` requests are in
 flight at once, each on its own stream, so a request that arrives while
 others run is admitted as soon as a stream slot and memory are free, and its

@@ -65,8 +65,19 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
     const int frame = blockIdx.y;
-    const int tile = blockIdx.x;
-    const TileGeom g = tile_geom<NT, PX>(a, blockIdx.x);
+    // (tile, split) item: from the work list or numbered tile-major; an item
+    // covers channel chunks [cb, ce) x transmits [tb, te) of its tile, and
+    // its windows are its own (no partial sums)
+    const int item = a.items ? a.items[blockIdx.x]
+                             : (int)blockIdx.z * (int)gridDim.x + (int)blockIdx.x;
+    const int tile = item / a.nsplit;
+    const int split = item - tile * a.nsplit;
+    const int ssc = split / a.nts;
+    const int cb = ssc * a.split_chunks * kChunk;
+    const int ce = min(a.C, cb + a.split_chunks * kChunk);
+    const int tb = (split - ssc * a.nts) * a.split_tx;
+    const int te = min(a.T, tb + a.split_tx);
+    const TileGeom g = tile_geom<NT, PX>(a, tile);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
     for (int i = tid; i < kChunk * slot; i += NT) win[i] = AdjEntry{0ull, 0ull};
 
@@ -92,7 +103,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     // workspace slots of (transmit t, channel c) for this tile
     auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };
 
-    for (int c0 = 0; c0 < a.C; c0 += kChunk) {
+    for (int c0 = cb; c0 < ce; c0 += kChunk) {
         __syncthreads();
         chunk_tables(a, g, c0, b_tab);
         __syncthreads();
@@ -106,8 +117,8 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             bmax = max(bmax, bj[j]);
         }
         if (!any_act) {  // nothing of this chunk reaches the tile
-            for (int w = tid; w < a.T * kChunk; w += NT) {
-                const int t = w >> kChunkLog2, c = c0 + (w & (kChunk - 1));
+            for (int w = tid; w < (te - tb) * kChunk; w += NT) {
+                const int t = tb + (w >> kChunkLog2), c = c0 + (w & (kChunk - 1));
                 if (c < a.C) a.ws_a0[slot_of(t, c)] = kNoWindow;
             }
             continue;
@@ -116,7 +127,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
 
-        for (int t = 0; t < a.T; ++t) {
+        for (int t = tb; t < te; ++t) {
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
             if (at + bmin > a.S - 2 || at + bmax + a.nst < 0) {  // nothing lands
                 if (tid < kChunk && c0 + tid < a.C) a.ws_a0[slot_of(t, c0 + tid)] = kNoWindow;
@@ -297,7 +308,8 @@ template <int MODE, int NT, int PX>
 hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
     hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX>, lds);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)a.F);
+    const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)
+                              : dim3((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
     hipLaunchKernelGGL((das_adjoint_kernel<MODE, NT, PX>), grid, dim3(NT), lds, s, a);
     return hipGetLastError();
 }

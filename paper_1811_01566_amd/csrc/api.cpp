@@ -875,8 +875,9 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
         return fail(WF_ERR_INVALID_ARG, "grad_rf overlaps g");
     wf::DasArgs a;
     TilePlan tp;
+    Geometry geo;
     if ((st = prepare_das(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                          mode == 1 ? angles_rad : nullptr, tref, grid, &a, &tp)) != WF_OK)
+                          mode == 1 ? angles_rad : nullptr, tref, grid, &a, &tp, &geo)) != WF_OK)
         return st;
     const size_t need = adjoint_ws_bytes(acq, tp);
     if (workspace_bytes < need)
@@ -892,6 +893,23 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
         (reinterpret_cast<uintptr_t>(a.ws_a0 + slots) + 255) & ~(uintptr_t)255);
     a.ws_gmax = gmax;
     a.F = 1;  // one frame per launch pair: the workspace holds one frame
+    // the forward's work split: items write disjoint windows, so the split
+    // needs no partial sums; windows of items left out of the work list are
+    // marked empty first (a fill kernel with kNoWindow's bit pattern)
+    const SplitPlan sp = plan_split(mode, geo, acq, grid, tp);
+    a.nsplit = sp.nsplit;
+    a.split_chunks = sp.chunks;
+    a.nts = sp.nts;
+    a.split_tx = sp.txs;
+    const long long all_items = (long long)a.ntiles * sp.nsplit;
+    const bool skipped = !sp.order.empty() && (long long)sp.order.size() < all_items;
+    if (!sp.order.empty() && (sp.nsplit > 1 || skipped)) {
+        if ((st = device_items(sp, &a.items)) != WF_OK) return st;
+        a.nitems = (int)sp.order.size();
+    }
+    float no_window;
+    static_assert(sizeof(no_window) == sizeof(wf::kNoWindow), "kNoWindow is 32-bit");
+    std::memcpy(&no_window, &wf::kNoWindow, sizeof no_window);
     // one buffer of 16-byte (G, H) entries: the bytes of the forward's two
     // buffers of 8-byte entries
     const size_t lds = tp.lds;
@@ -900,6 +918,9 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
         a.g = g + (size_t)f * grid->nz * grid->nx;
         hipError_t e = wf::launch_absmax(a.g, (size_t)grid->nz * grid->nx, gmax,
                                          (hipStream_t)stream);
+        if (e == hipSuccess && a.items && skipped)
+            e = wf::launch_fill(reinterpret_cast<float*>(a.ws_a0), slots, no_window,
+                                (hipStream_t)stream);
         if (e == hipSuccess)
             e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
         if (e == hipSuccess)

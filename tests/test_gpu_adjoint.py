@@ -23,7 +23,7 @@ import oracle
 import phantom
 from phantom.configs import subgrid
 from phantom.prepare import lighter
-from wfhelp import nl2, scan_from_workload
+from wfhelp import deep_pwi, nl2, scan_from_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +39,9 @@ CASES = {
     "tiny_pwi_apod": lambda: phantom.tiny_pwi(f_number=1.2, t0=-0.2e-6, tref="centre"),
     "pwi_sub": lambda: subgrid(phantom.get_workload("pwi").with_(n_tx=8, angles_deg=tuple(
         np.linspace(-16, 16, 8))), 300, 70, 200, 20),
+    # split into items, with items that run nothing left out of the work list
+    "stai_small": lambda: phantom.get_workload("stai_small"),
+    "deep_pwi": deep_pwi,
 }
 
 
@@ -46,6 +49,9 @@ CASES = {
 def test_adjoint_matches_oracle_and_dot_product(wf_gpu, name):
     torch = _t()
     w = CASES[name]()
+    if name in ("stai_small", "deep_pwi"):
+        info = wf_gpu.tile_info(scan_from_workload(w), w.n_s)
+        assert info["workgroups"] < info["ntz"] * info["ntx"] * info["nsplit"]
     rng = np.random.default_rng(4)
     g = rng.normal(size=(w.nz, w.nx)).astype(np.float32)
     r = rng.normal(size=(w.n_tx, w.n_ch, w.n_s)).astype(np.float32)

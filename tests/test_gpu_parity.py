@@ -19,7 +19,7 @@ import pytest
 import oracle
 import phantom
 from phantom.configs import subgrid
-from wfhelp import nl2, scan_from_workload
+from wfhelp import deep_pwi, nl2, scan_from_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -289,9 +289,7 @@ def test_das_record_limited_grid(wf_gpu):
     are cleared.  With and without a workspace the frame matches the
     oracle, and rows that no echo inside the record reaches are exactly 0."""
     torch = _torch()
-    w = phantom.tiny_pwi(name="deep_pwi", n_elem=32, n_tx=8, n_ch=32, n_s=512, nz=256, nx=64,
-                         z_min=1e-3, z_max=12e-3,
-                         angles_deg=tuple(float(a) for a in np.linspace(-10.0, 10.0, 8)))
+    w = deep_pwi()
     scan = scan_from_workload(w)
     info = wf_gpu.tile_info(scan, w.n_s)
     assert info["workgroups"] < info["ntz"] * info["ntx"] * info["nsplit"]

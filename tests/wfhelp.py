@@ -25,3 +25,16 @@ def nl2(a, b):
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def deep_pwi():
+    """A PWI grid reaching deeper than its record (512 samples, 1-12 mm):
+    the lower tiles receive no echo, so the DAS work split leaves them out
+    of its work list."""
+    import numpy as np
+
+    import phantom
+
+    return phantom.tiny_pwi(name="deep_pwi", n_elem=32, n_tx=8, n_ch=32, n_s=512, nz=256,
+                            nx=64, z_min=1e-3, z_max=12e-3,
+                            angles_deg=tuple(float(a) for a in np.linspace(-10.0, 10.0, 8)))

@@ -38,27 +38,23 @@ namespace {
 
 constexpr int kFlushLanes = 256;  // entries per flush row (power of two)
 
-// Window entry of the adjoint: 64-bit fixed-point G and H (scale 2^23 g24).
-struct AdjEntry {
-    unsigned long long g, h;
-};
-
-// Byte address of 16-byte window entry (u >> 23) at byte offset `off`.
-__device__ __forceinline__ uint32_t entry_addr16(uint32_t u, uint32_t off) {
-    const uint32_t idx = u >> kQBits;
-    uint32_t r;
-    asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(idx), "s"(off));
-    return r;
-}
+// Window sums of the adjoint: 64-bit fixed-point G and H (scale 2^23 g24),
+// in two separate arrays of 8-byte entries (all G windows, then all H
+// windows).  The lanes of a wave walk down one column, hitting entries about
+// 1.6 apart; with 8-byte entries one wave's atomics then span half the LDS
+// rows that interleaved 16-byte (G, H) entries would, and the bank
+// conflicts, which bound this kernel, fall with them.
+typedef unsigned long long u64;
 
 template <int MODE, int NT, int PX>
 __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
-    const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(AdjEntry);
-    AdjEntry* win = reinterpret_cast<AdjEntry*>(smem);
-    int4* m_tab = reinterpret_cast<int4*>(smem + buf_bytes);
+    const int nwin = kChunk * slot;  // entries of one array of windows
+    u64* gw = reinterpret_cast<u64*>(smem);  // G of window j: gw[j * slot + e]
+    u64* hw = gw + nwin;                     // H of window j: hw[j * slot + e]
+    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * (size_t)nwin * sizeof(u64));
     float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
     int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
     const uint32_t lds0 =
@@ -79,7 +75,8 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     const int te = min(a.T, tb + a.split_tx);
     const TileGeom g = tile_geom<NT, PX>(a, tile);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
-    for (int i = tid; i < kChunk * slot; i += NT) win[i] = AdjEntry{0ull, 0ull};
+    uint4* zw = reinterpret_cast<uint4*>(smem);  // both arrays, 16 bytes a store
+    for (int i = tid; i < nwin; i += NT) zw[i] = make_uint4(0u, 0u, 0u, 0u);
 
     PixelSet<PX> p;
     pixel_set<NT, PX, false>(a, g, p);
@@ -139,7 +136,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             // ---- scatter into the LDS windows (integer atomics) -------------
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 16u;
+                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
 #pragma unroll
                 for (int k = 0; k < PX; ++k) {
                     if (g24[k] == 0) continue;
@@ -148,9 +145,9 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                     // g24 * f23, both 24-bit signed: one 24 x 24-bit product
                     const unsigned long long h =
                         (unsigned long long)((long long)g24[k] * (long long)f23);
-                    AdjEntry* e = reinterpret_cast<AdjEntry*>(smem + (entry_addr16(u, off) - lds0));
-                    atomicAdd(&e->g, gG[k]);
-                    atomicAdd(&e->h, h);
+                    u64* e = reinterpret_cast<u64*>(smem + (entry_addr(u, off) - lds0));
+                    atomicAdd(e, gG[k]);
+                    atomicAdd(e + nwin, h);
                 }
             }
             __syncthreads();
@@ -166,17 +163,17 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                 if (c >= a.C || e >= ne) continue;
                 const int A0 = (at + b_tab[j]) & ~7;
                 const int s = A0 + e;
-                const AdjEntry* wj = win + j * slot;
+                const u64* gj = gw + j * slot;
+                const u64* hj = hw + j * slot;
                 long long v = 0;
-                if (e < a.nst && s >= 0 && s <= a.S - 2)
-                    v += (long long)wj[e].g - (long long)wj[e].h;
-                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)wj[e - 1].h;
+                if (e < a.nst && s >= 0 && s <= a.S - 2) v += (long long)gj[e] - (long long)hj[e];
+                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)hj[e - 1];
                 const size_t sl = slot_of(t, c);
                 a.ws_win[sl * ne + e] = (float)((double)v * unscale);
                 if (e == 0) a.ws_a0[sl] = A0;
             }
             __syncthreads();
-            for (int w = tid; w < kChunk * slot; w += NT) win[w] = AdjEntry{0ull, 0ull};
+            for (int w = tid; w < nwin; w += NT) zw[w] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();  // windows are zero before the next pass scatters
         }
     }

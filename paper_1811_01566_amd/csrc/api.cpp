@@ -910,7 +910,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     float no_window;
     static_assert(sizeof(no_window) == sizeof(wf::kNoWindow), "kNoWindow is 32-bit");
     std::memcpy(&no_window, &wf::kNoWindow, sizeof no_window);
-    // one buffer of 16-byte (G, H) entries: the bytes of the forward's two
+    // the 8-byte G and H windows take the bytes of the forward's two
     // buffers of 8-byte entries
     const size_t lds = tp.lds;
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;

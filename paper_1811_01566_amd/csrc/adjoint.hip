@@ -36,7 +36,14 @@
 namespace wf {
 namespace {
 
-constexpr int kFlushLanes = 256;  // entries per flush row (power of two)
+// A 64-bit integer of magnitude below 2^53 as a float: the magnitude's
+// 32-bit halves are converted (the high half exactly) and summed, so the
+// result is within about one ulp; full-rate FP32 instructions only.
+__device__ __forceinline__ float i64_to_float(long long v) {
+    const unsigned long long m = v < 0 ? 0ull - (unsigned long long)v : (unsigned long long)v;
+    const float f = fmaf((float)(unsigned)(m >> 32), 4294967296.0f, (float)(unsigned)m);
+    return v < 0 ? -f : f;
+}
 
 // Window sums of the adjoint: 64-bit fixed-point G and H (scale 2^23 g24),
 // in two separate arrays of 8-byte entries (all G windows, then all H
@@ -94,8 +101,10 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
         g24[k] = ((int)rintf(fminf(fmaxf(gv * to24, -8388607.0f), 8388607.0f)) << 8) >> 8;
         gG[k] = (unsigned long long)((long long)g24[k] << kQBits);
     }
-    // fixed point -> float: 2^-23 (fraction) * gmax / (2^23 - 1) (g24)
-    const double unscale = (double)gmax / (8388607.0 * 8388608.0);
+    // fixed point -> float: 2^-23 (fraction) * gmax / (2^23 - 1) (g24),
+    // applied as an exact 2^-46 and gmax 2^23 / (2^23 - 1), so nothing
+    // underflows or overflows that the gradient itself does not
+    const float gscale = gmax * (8388608.0f / 8388607.0f);
     const int ne = a.nst + 1;  // samples a window can touch
     // workspace slots of (transmit t, channel c) for this tile
     auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };
@@ -139,7 +148,6 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                 const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
 #pragma unroll
                 for (int k = 0; k < PX; ++k) {
-                    if (g24[k] == 0) continue;
                     const uint32_t u = tq[k] + rq[k][j];
                     const int f23 = (int)(u & 0x7FFFFFu);
                     // g24 * f23, both 24-bit signed: one 24 x 24-bit product
@@ -153,24 +161,24 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             __syncthreads();
 
             // ---- flush: sample A0 + e of every window to the workspace ------
-            // (lane -> entry e = e0 + lane % 256, channel j = lane / 256 + ...:
-            // consecutive lanes store consecutive workspace words)
-            for (int w = tid; w < kChunk * kFlushLanes * ((ne + kFlushLanes - 1) / kFlushLanes);
-                 w += NT) {
-                const int j = (w / kFlushLanes) & (kChunk - 1);
-                const int e = (w & (kFlushLanes - 1)) + kFlushLanes * (w / (kFlushLanes * kChunk));
+            // (a wave per channel: window base, workspace slot and A0 are
+            // wave-uniform; the lanes store consecutive workspace words)
+            for (int j = tid >> 6; j < kChunk; j += NT >> 6) {
                 const int c = c0 + j;
-                if (c >= a.C || e >= ne) continue;
-                const int A0 = (at + b_tab[j]) & ~7;
-                const int s = A0 + e;
+                if (c >= a.C) break;
+                const int A0 = __builtin_amdgcn_readfirstlane((at + b_tab[j]) & ~7);
+                const size_t sl = slot_of(t, c);
+                float* dst = a.ws_win + sl * ne;
                 const u64* gj = gw + j * slot;
                 const u64* hj = hw + j * slot;
-                long long v = 0;
-                if (e < a.nst && s >= 0 && s <= a.S - 2) v += (long long)gj[e] - (long long)hj[e];
-                if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)hj[e - 1];
-                const size_t sl = slot_of(t, c);
-                a.ws_win[sl * ne + e] = (float)((double)v * unscale);
-                if (e == 0) a.ws_a0[sl] = A0;
+                for (int e = tid & 63; e < ne; e += 64) {
+                    const int s = A0 + e;
+                    long long v = 0;
+                    if (e < a.nst && s >= 0 && s <= a.S - 2) v += (long long)gj[e] - (long long)hj[e];
+                    if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)hj[e - 1];
+                    dst[e] = ldexpf(i64_to_float(v), -46) * gscale;
+                }
+                if ((tid & 63) == 0) a.ws_a0[sl] = A0;
             }
             __syncthreads();
             for (int w = tid; w < nwin; w += NT) zw[w] = make_uint4(0u, 0u, 0u, 0u);

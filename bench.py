@@ -192,6 +192,7 @@ def cpu_baseline(w, rf, ncols):
                   f"{dt:.1f} s measured, scaled by {w.nx}/{ncols}",
         "s_per_frame": s_per_frame,
         "host_cpus": len(os.sched_getaffinity(0)),
+        "host_cpu_count": os.cpu_count(),
         "host_cpu_model": host_cpu_model(),
     }
 

@@ -61,6 +61,9 @@ SMALL = {
     "tiny_stai_apod_t0": lambda: phantom.tiny_stai(f_number=0.8, t0=0.3e-6),
     "tiny_pwi_apod_t0_centre": lambda: phantom.tiny_pwi(f_number=1.2, t0=-0.2e-6, tref="centre"),
     "single_pixel": lambda: phantom.tiny_pwi(nz=1, nx=1, z_min=0.5e-3, z_max=0.5e-3),
+    # the longest record the API takes (32768 samples), imaged near its end
+    "long_record": lambda: phantom.tiny_pwi(name="long_record", n_s=32768, nz=40, nx=7,
+                                            z_min=0.4500, z_max=0.4512),
     "stai_small": lambda: phantom.get_workload("stai_small"),
 }
 

@@ -2,7 +2,8 @@
 // Fig. 2: Analytic Signal -> Absolute Value -> Dynamic Adjustment; Hilbert
 // transform by FFT, Sec. II-B; dB clip, Sec. III).
 //
-// K3: one workgroup per image column.  The column is an nz-point complex
+// K3: one workgroup per group of 1, 2 or 4 adjacent image columns.  Each
+// column is an nz-point complex
 // FFT in LDS: a decimation-in-frequency forward pass (natural order in,
 // bit-reversed out), the one-sided multiplier applied at bit-reversed
 // positions, and a decimation-in-time inverse pass (bit-reversed in,
@@ -41,68 +42,84 @@ __device__ __forceinline__ float2 cmul_conj(float2 a, float2 w) {  // a * conj(w
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// One workgroup per column (and frame); log_n = log2(nz).  Radix-2
-// stages are fused in pairs (two spans per pass through LDS, 4 points per
-// lane in registers), halving the barriers; an odd stage count leaves one
-// single stage (the first forward one, the last inverse one).
-__global__ void __launch_bounds__(kEnvThreads)
+// CPW adjacent columns (and one frame) per workgroup of 256 CPW threads;
+// log_n = log2(nz).
+// A row's CPW values are contiguous in memory, so a wave's load or store
+// covers 64 / CPW rows with CPW-wide runs instead of 64 single words on 64
+// cache lines.  Radix-2 stages are fused in pairs (two spans per pass
+// through LDS, 4 points per lane in registers), halving the barriers; an odd
+// stage count leaves one single stage (the first forward one, the last
+// inverse one).  Column c of the workgroup lives at col[c n .. c n + n).
+template <int CPW>
+__global__ void __launch_bounds__(kEnvThreads * CPW)
     envelope_kernel(const float* bf, float* env, float* __restrict__ col_max, int nz, int nx,
                     int log_n) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kCpwLog2 = CPW == 4 ? 2 : (CPW == 2 ? 1 : 0);
     const int n = nz;
     const int half = n >> 1;
     float2* tw = reinterpret_cast<float2*>(smem);                 // [n/2]
-    float2* col = tw + (half > 0 ? half : 1);                     // [n]
-    __shared__ float red[kEnvThreads / 64];
+    float2* col = tw + (half > 0 ? half : 1);                     // [CPW][n]
+    constexpr int kThreads = kEnvThreads * CPW;  // 256 threads a column
+    __shared__ float red[kThreads / 64][CPW];
 
     const int tid = threadIdx.x;
-    const int x = blockIdx.x;
+    const int x0 = blockIdx.x * CPW;
     const int f = blockIdx.y;
-    const float* src = bf + (size_t)f * nz * nx + x;
-    float* dst = env + (size_t)f * nz * nx + x;
+    const float* src = bf + (size_t)f * nz * nx + x0;
+    float* dst = env + (size_t)f * nz * nx + x0;
 
     // W^k = exp(-2 pi i k / n)
-    for (int k = tid; k < half; k += kEnvThreads) {
+    for (int k = tid; k < half; k += kThreads) {
         float sn, cs;
         sincospif(-2.0f * (float)k / (float)n, &sn, &cs);
         tw[k] = make_float2(cs, sn);
     }
-    for (int z = tid; z < n; z += kEnvThreads) col[z] = make_float2(src[(size_t)z * nx], 0.0f);
+    // element i: row i / CPW, column i % CPW (columns fastest: contiguous)
+    for (int i = tid; i < (n << kCpwLog2); i += kThreads) {
+        const int z = i >> kCpwLog2, c = i & (CPW - 1);
+        col[(c << log_n) + z] = make_float2(x0 + c < nx ? src[(size_t)z * nx + c] : 0.0f, 0.0f);
+    }
     __syncthreads();
 
     // ---- forward DIF, spans n/2 .. 1 ------------------------------------
     int h = half;
     if (log_n & 1) {  // single stage of span n/2
-        for (int b = tid; b < half; b += kEnvThreads) {
-            const float2 x0 = col[b], x1 = col[b + h];
-            col[b] = cadd(x0, x1);
-            col[b + h] = cmul(csub(x0, x1), tw[b]);
+        for (int g = tid; g < (half << kCpwLog2); g += kThreads) {
+            const int b = g & (half - 1);
+            float2* cc = col + ((g >> (log_n - 1)) << log_n);
+            const float2 x0v = cc[b], x1v = cc[b + h];
+            cc[b] = cadd(x0v, x1v);
+            cc[b + h] = cmul(csub(x0v, x1v), tw[b]);
         }
         __syncthreads();
         h >>= 1;
     }
     for (; h >= 2; h >>= 2) {  // spans h and h/2 in one pass
         const int q = h >> 1, ts = half / h;
-        for (int g = tid; g < (n >> 2); g += kEnvThreads) {
+        for (int gg = tid; gg < (n >> 2 << kCpwLog2); gg += kThreads) {
+            const int g = gg & ((n >> 2) - 1);
+            float2* cc = col + ((gg >> (log_n - 2)) << log_n);
             const int pos = g & (q - 1);
             const int i0 = ((g - pos) << 2) + pos;  // block of 2h
-            float2 a0 = col[i0], a1 = col[i0 + q], a2 = col[i0 + h], a3 = col[i0 + h + q];
+            float2 a0 = cc[i0], a1 = cc[i0 + q], a2 = cc[i0 + h], a3 = cc[i0 + h + q];
             const float2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), tw[pos * ts]);
             const float2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), tw[(pos + q) * ts]);
             const float2 w2 = tw[pos * 2 * ts];
-            col[i0] = cadd(b0, b1);
-            col[i0 + q] = cmul(csub(b0, b1), w2);
-            col[i0 + h] = cadd(b2, b3);
-            col[i0 + h + q] = cmul(csub(b2, b3), w2);
+            cc[i0] = cadd(b0, b1);
+            cc[i0 + q] = cmul(csub(b0, b1), w2);
+            cc[i0 + h] = cadd(b2, b3);
+            cc[i0 + h + q] = cmul(csub(b2, b3), w2);
         }
         __syncthreads();
     }
     // one-sided spectrum: position p holds bin k = bitrev(p)
-    for (int p = tid; p < n; p += kEnvThreads) {
+    for (int i = tid; i < (n << kCpwLog2); i += kThreads) {
+        const int p = i & (n - 1);
         const int k = log_n > 0 ? (int)(__brev((unsigned)p) >> (32 - log_n)) : 0;
         const float gk = (k == 0 || k == half) ? 1.0f : (k < half ? 2.0f : 0.0f);
-        const float2 v = col[p];
-        col[p] = make_float2(v.x * gk, v.y * gk);
+        const float2 v = col[i];
+        col[i] = make_float2(v.x * gk, v.y * gk);
     }
     __syncthreads();
     // ---- inverse DIT with conjugate twiddles, spans 1 .. n/2 -------------
@@ -110,54 +127,61 @@ __global__ void __launch_bounds__(kEnvThreads)
     const int pairs = log_n >> 1;
     for (int st = 0; st < pairs; ++st, h <<= 2) {  // spans h and 2h in one pass
         const int ts = half / h, ts2 = ts >> 1;
-        for (int g = tid; g < (n >> 2); g += kEnvThreads) {
+        for (int gg = tid; gg < (n >> 2 << kCpwLog2); gg += kThreads) {
+            const int g = gg & ((n >> 2) - 1);
+            float2* cc = col + ((gg >> (log_n - 2)) << log_n);
             const int pos = g & (h - 1);
             const int i0 = ((g - pos) << 2) + pos;  // block of 4h
-            const float2 a0 = col[i0], a1 = col[i0 + h], a2 = col[i0 + 2 * h],
-                         a3 = col[i0 + 3 * h];
+            const float2 a0 = cc[i0], a1 = cc[i0 + h], a2 = cc[i0 + 2 * h], a3 = cc[i0 + 3 * h];
             const float2 w1 = tw[pos * ts];
             const float2 t1 = cmul_conj(a1, w1), t3 = cmul_conj(a3, w1);
             const float2 b0 = cadd(a0, t1), b1 = csub(a0, t1);
             const float2 b2 = cadd(a2, t3), b3 = csub(a2, t3);
             const float2 u2 = cmul_conj(b2, tw[pos * ts2]);
             const float2 u3 = cmul_conj(b3, tw[(pos + h) * ts2]);
-            col[i0] = cadd(b0, u2);
-            col[i0 + 2 * h] = csub(b0, u2);
-            col[i0 + h] = cadd(b1, u3);
-            col[i0 + 3 * h] = csub(b1, u3);
+            cc[i0] = cadd(b0, u2);
+            cc[i0 + 2 * h] = csub(b0, u2);
+            cc[i0 + h] = cadd(b1, u3);
+            cc[i0 + 3 * h] = csub(b1, u3);
         }
         __syncthreads();
     }
     if (log_n & 1) {  // last single stage, span n/2
-        for (int b = tid; b < half; b += kEnvThreads) {
-            const float2 t = cmul_conj(col[b + half], tw[b]);
-            const float2 x0 = col[b];
-            col[b] = cadd(x0, t);
-            col[b + half] = csub(x0, t);
+        for (int g = tid; g < (half << kCpwLog2); g += kThreads) {
+            const int b = g & (half - 1);
+            float2* cc = col + ((g >> (log_n - 1)) << log_n);
+            const float2 t = cmul_conj(cc[b + half], tw[b]);
+            const float2 x0v = cc[b];
+            cc[b] = cadd(x0v, t);
+            cc[b + half] = csub(x0v, t);
         }
         __syncthreads();
     }
-    // modulus, store, column maximum
+    // modulus, store (same contiguous order as the load), column maxima: a
+    // lane's elements all belong to column tid % CPW
     const float inv_n = 1.0f / (float)n;
+    const int cl = tid & (CPW - 1);
     float m = 0.0f;
-    for (int z = tid; z < n; z += kEnvThreads) {
-        const float2 v = col[z];
+    for (int i = tid; i < (n << kCpwLog2); i += kThreads) {
+        const int z = i >> kCpwLog2;
+        const float2 v = col[(cl << log_n) + z];
         const float e = sqrtf(fmaf(v.x, v.x, v.y * v.y)) * inv_n;
-        dst[(size_t)z * nx] = e;
+        if (x0 + cl < nx) dst[(size_t)z * nx + cl] = e;
         m = fmaxf(m, e);
     }
-    m = wave_max(m);
-    if ((tid & 63) == 0) red[tid >> 6] = m;
+#pragma unroll
+    for (int off = 32; off >= CPW; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((tid & 63) < CPW) red[tid >> 6][tid & 63] = m;
     __syncthreads();
-    if (tid == 0) {
-        float r = red[0];
-        for (int w = 1; w < kEnvThreads / 64; ++w) r = fmaxf(r, red[w]);
-        col_max[(size_t)f * nx + x] = r;
+    if (tid < CPW && x0 + tid < nx) {
+        float r = red[0][tid];
+        for (int w = 1; w < kThreads / 64; ++w) r = fmaxf(r, red[w][tid]);
+        col_max[(size_t)f * nx + x0 + tid] = r;
     }
 }
 
 constexpr int kLogThreads = 256;
-constexpr int kLogPerBlock = 4096;
+constexpr int kLogPerBlock = 1024;
 
 __global__ void __launch_bounds__(kLogThreads)
     log_compress_kernel(const float* env, const float* __restrict__ col_max,
@@ -177,11 +201,15 @@ __global__ void __launch_bounds__(kLogThreads)
     float* dst = out + (size_t)f * npix;
     const int p0 = blockIdx.x * kLogPerBlock;
     const int p1 = min(p0 + kLogPerBlock, npix);
-    const float lm = (m > 0.0f) ? log10f(m) : 0.0f;
+    // 20 log10(e / m) = 20 log10(2) (log2 e - log2 m), log2 by the hardware
+    // instruction (about 1 ulp, far inside the dB tolerance)
+    constexpr float kDbPerOctave = 6.020599913279624f;
+    const float lm = (m > 0.0f) ? __builtin_amdgcn_logf(m) : 0.0f;
     for (int p = p0 + tid; p < p1; p += kLogThreads) {
         const float e = src[p];
         float b = -dr_db;
-        if (e > 0.0f && m > 0.0f) b = fminf(fmaxf(20.0f * (log10f(e) - lm), -dr_db), 0.0f);
+        if (e > 0.0f && m > 0.0f)
+            b = fminf(fmaxf(kDbPerOctave * (__builtin_amdgcn_logf(e) - lm), -dr_db), 0.0f);
         dst[p] = b + shift;
     }
 }
@@ -192,10 +220,25 @@ hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, f
                            hipStream_t s) {
     int log_n = 0;
     while ((1 << log_n) < nz) ++log_n;
-    const size_t lds = (size_t)((nz / 2 > 0 ? nz / 2 : 1) + nz) * sizeof(float2);
-    dim3 grid((unsigned)nx, (unsigned)F);
-    hipLaunchKernelGGL(envelope_kernel, grid, dim3(kEnvThreads), lds, s, bf, env, col_max, nz, nx,
-                       log_n);
+    // the widest column group whose LDS stays within 64 KB and that still
+    // gives about a workgroup per CU (or more, for batches)
+    auto lds_of = [&](int cpw) {
+        return (size_t)((nz / 2 > 0 ? nz / 2 : 1) + (size_t)cpw * nz) * sizeof(float2);
+    };
+    auto groups = [&](int cpw) { return (long long)((nx + cpw - 1) / cpw) * F; };
+    int cpw = 1;
+    if (nz >= 4 && lds_of(4) <= 65536 && groups(4) >= 512) cpw = 4;
+    else if (nz >= 4 && lds_of(2) <= 65536 && groups(2) >= 256) cpw = 2;
+    const dim3 grid((unsigned)((nx + cpw - 1) / cpw), (unsigned)F);
+    if (cpw == 4)
+        hipLaunchKernelGGL(envelope_kernel<4>, grid, dim3(kEnvThreads * 4), lds_of(4), s, bf, env,
+                           col_max, nz, nx, log_n);
+    else if (cpw == 2)
+        hipLaunchKernelGGL(envelope_kernel<2>, grid, dim3(kEnvThreads * 2), lds_of(2), s, bf, env,
+                           col_max, nz, nx, log_n);
+    else
+        hipLaunchKernelGGL(envelope_kernel<1>, grid, dim3(kEnvThreads * 1), lds_of(1), s, bf, env,
+                           col_max, nz, nx, log_n);
     return hipGetLastError();
 }
 

@@ -169,8 +169,13 @@ def test_delays_full_size_pwi(wf_gpu):
 # envelope / log compression
 # ---------------------------------------------------------------------------
 
+# narrow frames take one column per workgroup; wide ones 2 (1024 x 513,
+# 512 x 129 x 8, 1024 x 512) or 4 (256 x 2050, 1024 x 512 x 8) adjacent
+# columns, with a ragged last group where nx is not a multiple
 @pytest.mark.parametrize("nz,nx,frames", [(64, 5, 1), (1024, 33, 2), (4096, 3, 1), (2, 4, 1),
-                                           (512, 7, 2), (2048, 5, 1), (4, 9, 1)])
+                                           (512, 7, 2), (2048, 5, 1), (4, 9, 1),
+                                           (1024, 513, 1), (512, 129, 8), (1024, 512, 1),
+                                           (256, 2050, 1), (1024, 512, 8)])
 def test_envelope_matches_oracle(wf_gpu, nz, nx, frames):
     torch = _torch()
     rng = np.random.default_rng(nz + nx)

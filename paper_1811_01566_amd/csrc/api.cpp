@@ -599,6 +599,9 @@ SplitPlan plan_split(int mode, const Geometry& g, const wf_acq* acq, const wf_gr
     const int by_lds = std::max(1, (int)(kLdsHard / std::max<size_t>(tp.lds, 1)));
     const int occ = std::min(by_waves, by_lds);
     if (tiles >= 8LL * 256 * occ) return base;
+    // the pass map holds tiles x chunks x (T + 1) counts: planning is skipped
+    // beyond 32 M of them (64 MB), where the tiles outnumber the slots anyway
+    if (tiles * nch * (T + 1LL) > (32LL << 20)) return base;
 
     std::string key;
     key_add(key, &mode, sizeof mode);
@@ -648,10 +651,11 @@ SplitPlan plan_split(int mode, const Geometry& g, const wf_acq* acq, const wf_gr
         }
     }
     // The modelled times are coarse (pass costs vary, the dispatcher is
-    // modelled only roughly): no split unless it costs 3 % more than the
-    // best candidate; otherwise, among the candidates within 5 % of the
-    // best, the one with the most items, whose heaviest-first list then
-    // balances best (measured: finer lists win where the estimate says tie).
+    // modelled only roughly): the grid stays unsplit unless running it so
+    // costs 3 % more than the best candidate; otherwise, among the
+    // candidates within 5 % of the best, the one with the most items, whose
+    // heaviest-first list then balances best (measured: finer lists win
+    // where the estimate says tie).
     double tmin = none_time;
     for (const auto& c : cand) tmin = std::min(tmin, c.second);
     SplitPlan best = cand[0].first;

@@ -26,6 +26,9 @@ namespace wf {
 namespace {
 
 constexpr int kEnvThreads = 256;
+#ifndef WF_ENV_GROUPS4
+#define WF_ENV_GROUPS4 512  // workgroups needed before 4-column groups are used
+#endif
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
@@ -41,6 +44,11 @@ __device__ __forceinline__ float2 cmul_conj(float2 a, float2 w) {  // a * conj(w
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// LDS index of column element i: one pad slot after every 16 elements (128
+// bytes), so the power-of-two strides of the butterflies (32 bytes and up
+// between lanes) spread over the banks instead of stacking 16 lanes on one.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
 // CPW adjacent columns (and one frame) per workgroup of 256 CPW threads;
 // log_n = log2(nz).
@@ -59,12 +67,19 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
     const int n = nz;
     const int half = n >> 1;
     float2* tw = reinterpret_cast<float2*>(smem);                 // [n/2]
-    float2* col = tw + (half > 0 ? half : 1);                     // [CPW][n]
+    float2* col = tw + (half > 0 ? half : 1);                     // [CPW][n], padded
     constexpr int kThreads = kEnvThreads * CPW;  // 256 threads a column
     __shared__ float red[kThreads / 64][CPW];
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * CPW;
+    // workgroups are dealt to the 8 XCDs round-robin; XCD k takes the
+    // contiguous block of column groups [start_k, start_k + count_k), so the
+    // columns of a cache line meet in one L2 (dealt in order, each of the 8
+    // L2s would fetch and write back every line: 8x the traffic)
+    const int ng = (int)gridDim.x;
+    const int xk = (int)blockIdx.x & 7, xi = (int)blockIdx.x >> 3;
+    const int grp = xk * (ng >> 3) + min(xk, ng & 7) + xi;
+    const int x0 = grp * CPW;
     const int f = blockIdx.y;
     const float* src = bf + (size_t)f * nz * nx + x0;
     float* dst = env + (size_t)f * nz * nx + x0;
@@ -78,7 +93,8 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
     // element i: row i / CPW, column i % CPW (columns fastest: contiguous)
     for (int i = tid; i < (n << kCpwLog2); i += kThreads) {
         const int z = i >> kCpwLog2, c = i & (CPW - 1);
-        col[(c << log_n) + z] = make_float2(x0 + c < nx ? src[(size_t)z * nx + c] : 0.0f, 0.0f);
+        col[pad((c << log_n) + z)] =
+            make_float2(x0 + c < nx ? src[(size_t)z * nx + c] : 0.0f, 0.0f);
     }
     __syncthreads();
 
@@ -87,10 +103,10 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
     if (log_n & 1) {  // single stage of span n/2
         for (int g = tid; g < (half << kCpwLog2); g += kThreads) {
             const int b = g & (half - 1);
-            float2* cc = col + ((g >> (log_n - 1)) << log_n);
-            const float2 x0v = cc[b], x1v = cc[b + h];
-            cc[b] = cadd(x0v, x1v);
-            cc[b + h] = cmul(csub(x0v, x1v), tw[b]);
+            const int cb = (g >> (log_n - 1)) << log_n;
+            const float2 x0v = col[pad(cb + b)], x1v = col[pad(cb + b + h)];
+            col[pad(cb + b)] = cadd(x0v, x1v);
+            col[pad(cb + b + h)] = cmul(csub(x0v, x1v), tw[b]);
         }
         __syncthreads();
         h >>= 1;
@@ -99,17 +115,18 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
         const int q = h >> 1, ts = half / h;
         for (int gg = tid; gg < (n >> 2 << kCpwLog2); gg += kThreads) {
             const int g = gg & ((n >> 2) - 1);
-            float2* cc = col + ((gg >> (log_n - 2)) << log_n);
+            const int cb = (gg >> (log_n - 2)) << log_n;
             const int pos = g & (q - 1);
-            const int i0 = ((g - pos) << 2) + pos;  // block of 2h
-            float2 a0 = cc[i0], a1 = cc[i0 + q], a2 = cc[i0 + h], a3 = cc[i0 + h + q];
+            const int i0 = cb + ((g - pos) << 2) + pos;  // block of 2h
+            const int j0 = pad(i0), j1 = pad(i0 + q), j2 = pad(i0 + h), j3 = pad(i0 + h + q);
+            float2 a0 = col[j0], a1 = col[j1], a2 = col[j2], a3 = col[j3];
             const float2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), tw[pos * ts]);
             const float2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), tw[(pos + q) * ts]);
             const float2 w2 = tw[pos * 2 * ts];
-            cc[i0] = cadd(b0, b1);
-            cc[i0 + q] = cmul(csub(b0, b1), w2);
-            cc[i0 + h] = cadd(b2, b3);
-            cc[i0 + h + q] = cmul(csub(b2, b3), w2);
+            col[j0] = cadd(b0, b1);
+            col[j1] = cmul(csub(b0, b1), w2);
+            col[j2] = cadd(b2, b3);
+            col[j3] = cmul(csub(b2, b3), w2);
         }
         __syncthreads();
     }
@@ -118,8 +135,8 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
         const int p = i & (n - 1);
         const int k = log_n > 0 ? (int)(__brev((unsigned)p) >> (32 - log_n)) : 0;
         const float gk = (k == 0 || k == half) ? 1.0f : (k < half ? 2.0f : 0.0f);
-        const float2 v = col[i];
-        col[i] = make_float2(v.x * gk, v.y * gk);
+        const float2 v = col[pad(i)];
+        col[pad(i)] = make_float2(v.x * gk, v.y * gk);
     }
     __syncthreads();
     // ---- inverse DIT with conjugate twiddles, spans 1 .. n/2 -------------
@@ -129,31 +146,32 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
         const int ts = half / h, ts2 = ts >> 1;
         for (int gg = tid; gg < (n >> 2 << kCpwLog2); gg += kThreads) {
             const int g = gg & ((n >> 2) - 1);
-            float2* cc = col + ((gg >> (log_n - 2)) << log_n);
+            const int cb = (gg >> (log_n - 2)) << log_n;
             const int pos = g & (h - 1);
-            const int i0 = ((g - pos) << 2) + pos;  // block of 4h
-            const float2 a0 = cc[i0], a1 = cc[i0 + h], a2 = cc[i0 + 2 * h], a3 = cc[i0 + 3 * h];
+            const int i0 = cb + ((g - pos) << 2) + pos;  // block of 4h
+            const int j0 = pad(i0), j1 = pad(i0 + h), j2 = pad(i0 + 2 * h), j3 = pad(i0 + 3 * h);
+            const float2 a0 = col[j0], a1 = col[j1], a2 = col[j2], a3 = col[j3];
             const float2 w1 = tw[pos * ts];
             const float2 t1 = cmul_conj(a1, w1), t3 = cmul_conj(a3, w1);
             const float2 b0 = cadd(a0, t1), b1 = csub(a0, t1);
             const float2 b2 = cadd(a2, t3), b3 = csub(a2, t3);
             const float2 u2 = cmul_conj(b2, tw[pos * ts2]);
             const float2 u3 = cmul_conj(b3, tw[(pos + h) * ts2]);
-            cc[i0] = cadd(b0, u2);
-            cc[i0 + 2 * h] = csub(b0, u2);
-            cc[i0 + h] = cadd(b1, u3);
-            cc[i0 + 3 * h] = csub(b1, u3);
+            col[j0] = cadd(b0, u2);
+            col[j2] = csub(b0, u2);
+            col[j1] = cadd(b1, u3);
+            col[j3] = csub(b1, u3);
         }
         __syncthreads();
     }
     if (log_n & 1) {  // last single stage, span n/2
         for (int g = tid; g < (half << kCpwLog2); g += kThreads) {
             const int b = g & (half - 1);
-            float2* cc = col + ((g >> (log_n - 1)) << log_n);
-            const float2 t = cmul_conj(cc[b + half], tw[b]);
-            const float2 x0v = cc[b];
-            cc[b] = cadd(x0v, t);
-            cc[b + half] = csub(x0v, t);
+            const int cb = (g >> (log_n - 1)) << log_n;
+            const float2 t = cmul_conj(col[pad(cb + b + half)], tw[b]);
+            const float2 x0v = col[pad(cb + b)];
+            col[pad(cb + b)] = cadd(x0v, t);
+            col[pad(cb + b + half)] = csub(x0v, t);
         }
         __syncthreads();
     }
@@ -164,7 +182,7 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
     float m = 0.0f;
     for (int i = tid; i < (n << kCpwLog2); i += kThreads) {
         const int z = i >> kCpwLog2;
-        const float2 v = col[(cl << log_n) + z];
+        const float2 v = col[pad((cl << log_n) + z)];
         const float e = sqrtf(fmaf(v.x, v.x, v.y * v.y)) * inv_n;
         if (x0 + cl < nx) dst[(size_t)z * nx + cl] = e;
         m = fmaxf(m, e);
@@ -223,11 +241,12 @@ hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, f
     // the widest column group whose LDS stays within 64 KB and that still
     // gives about a workgroup per CU (or more, for batches)
     auto lds_of = [&](int cpw) {
-        return (size_t)((nz / 2 > 0 ? nz / 2 : 1) + (size_t)cpw * nz) * sizeof(float2);
+        const size_t cols = (size_t)cpw * nz;
+        return (size_t)((nz / 2 > 0 ? nz / 2 : 1) + cols + (cols >> 4) + 1) * sizeof(float2);
     };
     auto groups = [&](int cpw) { return (long long)((nx + cpw - 1) / cpw) * F; };
     int cpw = 1;
-    if (nz >= 4 && lds_of(4) <= 65536 && groups(4) >= 512) cpw = 4;
+    if (nz >= 4 && lds_of(4) <= 65536 && groups(4) >= WF_ENV_GROUPS4) cpw = 4;
     else if (nz >= 4 && lds_of(2) <= 65536 && groups(2) >= 256) cpw = 2;
     const dim3 grid((unsigned)((nx + cpw - 1) / cpw), (unsigned)F);
     if (cpw == 4)

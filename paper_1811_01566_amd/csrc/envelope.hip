@@ -72,14 +72,10 @@ __global__ void __launch_bounds__(kEnvThreads * CPW)
     __shared__ float red[kThreads / 64][CPW];
 
     const int tid = threadIdx.x;
-    // workgroups are dealt to the 8 XCDs round-robin; XCD k takes the
-    // contiguous block of column groups [start_k, start_k + count_k), so the
-    // columns of a cache line meet in one L2 (dealt in order, each of the 8
-    // L2s would fetch and write back every line: 8x the traffic)
-    const int ng = (int)gridDim.x;
-    const int xk = (int)blockIdx.x & 7, xi = (int)blockIdx.x >> 3;
-    const int grp = xk * (ng >> 3) + min(xk, ng & 7) + xi;
-    const int x0 = grp * CPW;
+    // each XCD takes a contiguous block of column groups, so the columns of
+    // a cache line meet in one L2 (dealt in order, each of the 8 L2s would
+    // fetch and write back every line: 8x the traffic)
+    const int x0 = xcd_contiguous((int)blockIdx.x, (int)gridDim.x) * CPW;
     const int f = blockIdx.y;
     const float* src = bf + (size_t)f * nz * nx + x0;
     float* dst = env + (size_t)f * nz * nx + x0;

@@ -206,7 +206,9 @@ __global__ void __launch_bounds__(kMomThreads)
     moments_kernel(const float* __restrict__ env, float* __restrict__ out, int nz, int nx,
                    int wz, int wx, int sz, int sx, int mz, int mx) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int i = blockIdx.x;  // window row
+    // window row; each XCD takes a contiguous block of them, so the wz / sz
+    // window rows reading each envelope row meet in one L2
+    const int i = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
     const int f = blockIdx.y;
     const int j0 = blockIdx.z * kMomCols;  // first output column of this workgroup
     const int jn = min(kMomCols, mx - j0);

@@ -26,6 +26,17 @@ constexpr int kQBits = 23;
 // Adjoint workspace mark: the (transmit, channel, tile) window adds nothing.
 constexpr int kNoWindow = -0x40000000;
 
+// Workgroups are dealt to the 8 XCDs round-robin along the dispatch order.
+// For block b of n along the fastest grid dimension this returns the index
+// to work on such that XCD k takes the contiguous range of indices
+// [k floor(n/8) + min(k, n mod 8), ...) of length floor(n/8) + (k < n mod 8):
+// neighbouring indices, which read or write the same cache lines, then
+// meet in one L2 instead of all eight.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+    const int k = b & 7;
+    return k * (n >> 3) + (k < (n & 7) ? k : (n & 7)) + (b >> 3);
+}
+
 // Per-transmit constants of a geometry, in samples (distances scaled by
 // fs / c), split into float-float pairs on the host from double.
 //   PWI:  v0 = (C0.hi, C0.lo, Az.hi, Az.lo), v1 = (Ax.hi, Ax.lo, 0, 0) with

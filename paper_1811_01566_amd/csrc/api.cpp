@@ -284,7 +284,10 @@ size_t das_lds_bytes(int slot, int T) {
 
 // LDS per workgroup: plans within 64 KB are preferred; gfx950 allows up to
 // 160 KB for a single workgroup, used only when no smaller plan fits.
-constexpr size_t kLdsSoft = 65536;
+#ifndef WF_LDS_SOFT
+#define WF_LDS_SOFT 65536
+#endif
+constexpr size_t kLdsSoft = WF_LDS_SOFT;
 constexpr size_t kLdsHard = 163840;
 
 #ifndef WF_DAS_ALLOW_1024

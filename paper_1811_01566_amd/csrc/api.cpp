@@ -282,12 +282,7 @@ size_t das_lds_bytes(int slot, int T) {
     return 2 * (size_t)wf::kChunk * slot * 8 + (size_t)T * 32 + (size_t)wf::kChunk * 8;
 }
 
-// LDS per workgroup: plans within 64 KB are preferred; gfx950 allows up to
-// 160 KB for a single workgroup, used only when no smaller plan fits.
-#ifndef WF_LDS_SOFT
-#define WF_LDS_SOFT 65536
-#endif
-constexpr size_t kLdsSoft = WF_LDS_SOFT;
+// LDS of one CU on gfx950 (and the most a single workgroup may take).
 constexpr size_t kLdsHard = 163840;
 
 #ifndef WF_DAS_ALLOW_1024
@@ -301,7 +296,10 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
     // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
     // with twice the waves per workgroup, 1024 x 2 twice the tile
     const int shapes[4][2] = {{WF_DAS_ALLOW_1024 ? 1024 : 512, 2}, {512, 2}, {256, 4}, {256, 1}};
-    for (size_t limit : {kLdsSoft, kLdsHard}) {
+    // a plan must leave LDS for 8 resident waves per CU (two 256-thread
+    // workgroups, or one of 512 or 1024 threads); one with 4 is taken only
+    // when nothing else fits
+    for (int min_waves : {8, 4}) {
         double best_score = -1.0;
         for (const auto& sh : shapes) {
             const int nt = sh[0], px = sh[1];
@@ -320,11 +318,12 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
                 const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
                 if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
                 const size_t lds = das_lds_bytes(slot, acq->n_tx);
-                // a 16-wave workgroup fills its CU alone: no need to leave
-                // LDS for a second one
-                if (lds > (nt == 1024 ? kLdsHard : limit)) continue;
+                if (lds > kLdsHard || (int)(kLdsHard / lds) * (nt / 64) < min_waves) continue;
                 const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
-                const double wgs = (double)ntz * ntx * acq->n_frames;
+                // one frame's workgroups: the plan (window bases, so the
+                // rounding of the delays) must not depend on the frame count,
+                // or a batch and its frames one by one would differ
+                const double wgs = (double)ntz * ntx;
                 // pixels served per staged sample, discounted when there are
                 // too few workgroups to give every CU 16 waves; ties keep the
                 // earlier shape

@@ -162,26 +162,34 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
 
             // ---- flush: sample A0 + e of every window to the workspace ------
             // (a wave per channel: window base, workspace slot and A0 are
-            // wave-uniform; the lanes store consecutive workspace words)
+            // wave-uniform; the lanes store consecutive workspace words).
+            // The wave then clears the windows it owns: its LDS reads are
+            // done in order before its stores, and no other wave touches
+            // them until the barrier, so no barrier is needed in between.
             for (int j = tid >> 6; j < kChunk; j += NT >> 6) {
                 const int c = c0 + j;
-                if (c >= a.C) break;
-                const int A0 = __builtin_amdgcn_readfirstlane((at + b_tab[j]) & ~7);
-                const size_t sl = slot_of(t, c);
-                float* dst = a.ws_win + sl * ne;
-                const u64* gj = gw + j * slot;
-                const u64* hj = hw + j * slot;
-                for (int e = tid & 63; e < ne; e += 64) {
-                    const int s = A0 + e;
-                    long long v = 0;
-                    if (e < a.nst && s >= 0 && s <= a.S - 2) v += (long long)gj[e] - (long long)hj[e];
-                    if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)hj[e - 1];
-                    dst[e] = ldexpf(i64_to_float(v), -46) * gscale;
+                u64* gj = gw + j * slot;
+                u64* hj = hw + j * slot;
+                if (c < a.C) {
+                    const int A0 = __builtin_amdgcn_readfirstlane((at + b_tab[j]) & ~7);
+                    const size_t sl = slot_of(t, c);
+                    float* dst = a.ws_win + sl * ne;
+                    for (int e = tid & 63; e < ne; e += 64) {
+                        const int s = A0 + e;
+                        long long v = 0;
+                        if (e < a.nst && s >= 0 && s <= a.S - 2)
+                            v += (long long)gj[e] - (long long)hj[e];
+                        if (e >= 1 && s - 1 >= 0 && s - 1 <= a.S - 2) v += (long long)hj[e - 1];
+                        dst[e] = ldexpf(i64_to_float(v), -46) * gscale;
+                    }
+                    if ((tid & 63) == 0) a.ws_a0[sl] = A0;
                 }
-                if ((tid & 63) == 0) a.ws_a0[sl] = A0;
+                // slot is even and j slot 8 bytes a multiple of 16: 16-byte stores
+                for (int e = 2 * (tid & 63); e < slot; e += 128) {
+                    *reinterpret_cast<uint4*>(gj + e) = make_uint4(0u, 0u, 0u, 0u);
+                    *reinterpret_cast<uint4*>(hj + e) = make_uint4(0u, 0u, 0u, 0u);
+                }
             }
-            __syncthreads();
-            for (int w = tid; w < nwin; w += NT) zw[w] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();  // windows are zero before the next pass scatters
         }
     }

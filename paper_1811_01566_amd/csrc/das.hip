@@ -48,7 +48,11 @@ enum : int {
 // ---------------------------------------------------------------------------
 // K2: gather / interpolate / accumulate
 // ---------------------------------------------------------------------------
-template <int MODE, typename RT, int NT, int PX, int NG, int OP>
+// FG frames per workgroup: the frames of a batch share the geometry, so a
+// group reuses each chunk's receive delays and each pass's transmit delays;
+// every frame keeps its own accumulation order, so a batch equals its
+// frames one by one bit for bit.
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG>
 __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
@@ -62,7 +66,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const uint32_t lds0 =
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
-    const int frame = blockIdx.y;
+    const int frame0 = (int)blockIdx.y * FG;
+    const int fgc = min(FG, a.F - frame0);  // frames of this group
     // (tile, split) item of this workgroup: from the work list, or numbered
     // tile-major in dispatch order (x fastest, then z)
     const int item = a.items ? a.items[blockIdx.x]
@@ -82,10 +87,13 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
 
     PixelSet<PX> p;
     pixel_set<NT, PX>(a, g, p);
-    float acc[PX];
+    float acc[FG][PX];
 #pragma unroll
-    for (int k = 0; k < PX; ++k) acc[k] = 0.0f;
-    const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame * a.T * a.C * a.S;
+    for (int g = 0; g < FG; ++g)
+#pragma unroll
+        for (int k = 0; k < PX; ++k) acc[g][k] = 0.0f;
+    const size_t frame_elems = (size_t)a.T * a.C * a.S;
+    const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame0 * frame_elems;
     const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * NT)
 
     // split: this workgroup sums channel chunks [cb, ce) x transmits [tb, te)
@@ -141,9 +149,12 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // global -> registers for pass t (nothing written yet); a group
         // outside the record reads zeros through the buffer range check
         RawGroup<RT> raw[NG];
-        auto issue = [&](int t) {
+        auto issue = [&](int t, int g) {  // pass t of frame frame0 + g
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
-            const __amdgpu_buffer_rsrc_t rsrc = rf_rsrc(rf_frame + (size_t)t * a.C * a.S, rec_bytes);
+            // a ragged last group repeats its last frame (results not written)
+            const size_t fo = FG == 1 ? 0 : (size_t)min(g, fgc - 1) * frame_elems;
+            const __amdgpu_buffer_rsrc_t rsrc =
+                rf_rsrc(rf_frame + fo + (size_t)t * a.C * a.S, rec_bytes);
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
@@ -189,63 +200,89 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         int t = next_active(tb);
         if (t >= te) continue;  // no transmit reaches this tile through this chunk
 
-        // software pipeline over transmit passes, two LDS buffers: commit
-        // pass t into buffer `cur` (last read two passes ago, before the
-        // barrier of the previous iteration), barrier, then issue the loads
-        // of the next pass so that they fly while pass t is accumulated.  The
-        // first pass's loads fly while the receive delays are formed.
-        issue(t);
+        // software pipeline over the passes, two LDS buffers: commit a pass
+        // into buffer `cur` (last read two passes ago, before the barrier of
+        // the previous pass), barrier, then issue the loads of the next pass
+        // so that they fly while this one is accumulated.  The first pass's
+        // loads fly while the receive delays are formed.
+        issue(t, 0);
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
         int cur = 0;
+        // With FG > 1 the passes run (transmit t, frame g) with g fastest;
+        // the frame loop stays rolled, its accumulators rotating by one
+        // frame per pass, so that only the transmit delays are held across
+        // frames.
         while (t < te) {
             const int tn = next_active(t + 1);
-            commit(t, cur);
-            __syncthreads();
-            if (tn < te) issue(tn);
-            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
             uint32_t tq[PX];
-            tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+            if (FG > 1) {
+                const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+                tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+            }
+#pragma unroll 1
+            for (int g = 0; g < FG; ++g) {
+                commit(t, cur);
+                __syncthreads();
+                if (g + 1 < FG) issue(t, g + 1);
+                else if (tn < te) issue(tn, 0);
+                const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+                if (FG == 1) tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+                // 1024-thread workgroups have no registers to keep the sums of
+                // transmit and receive delays across frames: recompute them
+                if (FG > 1 && NT == 1024)
+#pragma unroll
+                    for (int k = 0; k < PX; ++k) opaque_u(tq[k]);
 
-            // ---- gather / interpolate / accumulate -------------------------
-            // batches of LDS reads are issued before their FMAs so that
-            // several reads are in flight per wave
-            const uint32_t base = lds0 + (uint32_t)cur * buf_bytes;
-            constexpr int kJB = (WF_DAS_READS / PX) < 1 ? 1 : (WF_DAS_READS / PX);
+                // ---- gather / interpolate / accumulate -------------------------
+                // batches of LDS reads are issued before their FMAs so that
+                // several reads are in flight per wave
+                const uint32_t base = lds0 + (uint32_t)cur * buf_bytes;
+                constexpr int kJB = (WF_DAS_READS / PX) < 1 ? 1 : (WF_DAS_READS / PX);
 #pragma unroll
-            for (int j0 = 0; j0 < kChunk; j0 += kJB) {
-                float2 ed[kJB][PX];
-                float f1[kJB][PX];
-                float nf[kJB];
+                for (int j0 = 0; j0 < kChunk; j0 += kJB) {
+                    float2 ed[kJB][PX];
+                    float f1[kJB][PX];
+                    float nf[kJB];
 #pragma unroll
-                for (int jj = 0; jj < kJB; ++jj) {
-                    const int j = j0 + jj;
-                    const uint32_t off =
-                        base + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
-                    if (OP == kOpDydc) nf[jj] = (float)(at + bj[j]) + a.t0fs;
+                    for (int jj = 0; jj < kJB; ++jj) {
+                        const int j = j0 + jj;
+                        const uint32_t off =
+                            base + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+                        if (OP == kOpDydc) nf[jj] = (float)(at + bj[j]) + a.t0fs;
+#pragma unroll
+                        for (int k = 0; k < PX; ++k) {
+                            const uint32_t u = tq[k] + rq[k][j];
+                            if (OP == kOpValue)
+                                f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
+                            else  // absolute fractional sample index + t0 fs
+                                f1[jj][k] = fmaf((float)u, 1.0f / kQScale, nf[jj]);
+                            const v2f e2 = *reinterpret_cast<const __attribute__((address_space(3))) v2f*>(
+                                (uintptr_t)entry_addr(u, off));
+                            ed[jj][k] = make_float2(e2.x, e2.y);
+                        }
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < kJB; ++jj)
+#pragma unroll
+                        for (int k = 0; k < PX; ++k) {
+                            if (OP == kOpValue)
+                                acc[0][k] += fmaf(f1[jj][k], ed[jj][k].y, ed[jj][k].x);
+                            else
+                                acc[0][k] = fmaf(ed[jj][k].y, f1[jj][k], acc[0][k]);
+                        }
+                }
+                cur ^= 1;
+                if (FG > 1) {
 #pragma unroll
                     for (int k = 0; k < PX; ++k) {
-                        const uint32_t u = tq[k] + rq[k][j];
-                        if (OP == kOpValue)
-                            f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
-                        else  // absolute fractional sample index + t0 fs
-                            f1[jj][k] = fmaf((float)u, 1.0f / kQScale, nf[jj]);
-                        const v2f e2 = *reinterpret_cast<const __attribute__((address_space(3))) v2f*>(
-                            (uintptr_t)entry_addr(u, off));
-                        ed[jj][k] = make_float2(e2.x, e2.y);
+                        const float x = acc[0][k];
+#pragma unroll
+                        for (int h = 0; h + 1 < FG; ++h) acc[h][k] = acc[h + 1][k];
+                        acc[FG - 1][k] = x;
                     }
                 }
-#pragma unroll
-                for (int jj = 0; jj < kJB; ++jj)
-#pragma unroll
-                    for (int k = 0; k < PX; ++k) {
-                        if (OP == kOpValue)
-                            acc[k] += fmaf(f1[jj][k], ed[jj][k].y, ed[jj][k].x);
-                        else
-                            acc[k] = fmaf(ed[jj][k].y, f1[jj][k], acc[k]);
-                    }
             }
-            cur ^= 1;
             t = tn;
         }
     }
@@ -253,8 +290,13 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const float scale = (OP == kOpValue) ? 1.0f : a.neg_inv_c;
     float* dst = a.partial ? a.partial + (size_t)split * a.F * a.nz * a.nx : a.out;
 #pragma unroll
-    for (int k = 0; k < PX; ++k)
-        if (p.valid[k]) dst[((size_t)frame * a.nz + p.iz[k]) * a.nx + p.ix[k]] = acc[k] * scale;
+    for (int g = 0; g < FG; ++g)
+        if (g < fgc)
+#pragma unroll
+            for (int k = 0; k < PX; ++k)
+                if (p.valid[k])
+                    dst[((size_t)(frame0 + g) * a.nz + p.iz[k]) * a.nx + p.ix[k]] =
+                        acc[g][k] * scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -298,14 +340,23 @@ hipError_t allow_lds(K kernel, size_t lds) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int MODE, typename RT, int NT, int PX, int NG, int OP>
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG = 1>
 hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
-    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP>, lds);
+    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG>, lds);
     if (e != hipSuccess) return e;
-    const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)
-                              : dim3((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
-    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP>), grid, dim3(NT), lds, s, a);
+    const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
+    const dim3 grid = a.items ? dim3((unsigned)a.nitems, groups, 1u)
+                              : dim3((unsigned)(a.ntz * a.ntx), groups, (unsigned)a.nsplit);
+    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG>), grid, dim3(NT), lds, s, a);
     return hipGetLastError();
+}
+
+// Batches of the large-tile shapes run 4 frames per workgroup (the value
+// gather only; d y / d c keeps one).
+template <int MODE, typename RT, int NT, int OP>
+hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
+    if (OP == kOpValue && a.F > 1) return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
+    return launch_one<MODE, RT, NT, 2, 2, OP, 1>(a, lds, s);
 }
 
 // (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 512 x 2
@@ -313,8 +364,8 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
 // tiles for coarse grids)
 template <int MODE, typename RT, int OP>
 hipError_t launch_px(int nt, int px, int groups, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024) return launch_one<MODE, RT, 1024, 2, 2, OP>(a, lds, s);
-    if (nt == 512) return launch_one<MODE, RT, 512, 2, 2, OP>(a, lds, s);
+    if (nt == 1024) return launch_large<MODE, RT, 1024, OP>(a, lds, s);
+    if (nt == 512) return launch_large<MODE, RT, 512, OP>(a, lds, s);
     if (px == 4)
         return groups <= 2 ? launch_one<MODE, RT, 256, 4, 2, OP>(a, lds, s)
                            : launch_one<MODE, RT, 256, 4, 4, OP>(a, lds, s);

@@ -71,6 +71,7 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 // samples then stays one float subtract, where the optimiser would rewrite
 // it as an integer subtract plus a second convert.
 __device__ __forceinline__ void opaque(float& x) { asm("" : "+v"(x)); }
+__device__ __forceinline__ void opaque_u(uint32_t& x) { asm("" : "+v"(x)); }
 
 // Byte address of window entry (u >> 23) at byte offset `off`: one shift
 // and one shift-add (the compiler would otherwise emit shift, mask, add).

@@ -120,15 +120,25 @@ def test_das_rf_dtypes(wf_gpu, dtype):
     assert err <= NL2_TOL
 
 
-def test_das_multi_frame_matches_single(wf_gpu):
-    w = subgrid(_lighter(phantom.get_workload("pwi")).with_(n_frames=3), 200, 64, 300, 32)
+# Batches run several frames per workgroup on the large tiles (groups of 4,
+# the last one ragged here); every frame must equal its single-frame run.
+# The extra cases draw uniform random records: the check needs no echoes.
+@pytest.mark.parametrize("name,frames,z0,nz,x0,nx,rand", [
+    ("pwi", 3, 200, 64, 300, 32, False),        # 1024-thread tiles, one ragged group
+    ("pwi", 5, 200, 128, 300, 96, True),        # 1024-thread tiles, groups of 4 and 1
+    ("stai_full", 6, 100, 128, 60, 64, True),   # 512-thread tiles, groups of 4 and 2
+])
+def test_das_multi_frame_matches_single(wf_gpu, name, frames, z0, nz, x0, nx, rand):
+    w = subgrid(_lighter(phantom.get_workload(name)).with_(n_frames=frames), z0, nz, x0, nx)
+    if rand:
+        w = w.with_(phantom="random")
     rf = phantom.synth_rf(w)
     y = _run_das(wf_gpu, w, rf)
-    for f in range(3):
+    for f in range(frames):
         y1 = _run_das(wf_gpu, w.with_(n_frames=1), rf[f])[0]
-        assert np.array_equal(y[f], y1)
-    ref = oracle.das_workload(rf[1].astype(np.float64), w.with_(n_frames=1))
-    assert nl2(y[1], ref) <= NL2_TOL
+        assert np.array_equal(y[f], y1), f
+    ref = oracle.das_workload(rf[frames - 1].astype(np.float64), w.with_(n_frames=1))
+    assert nl2(y[frames - 1], ref) <= NL2_TOL
 
 
 def test_das_deterministic_and_zero(wf_gpu):

@@ -53,15 +53,21 @@ __device__ __forceinline__ float i64_to_float(long long v) {
 // conflicts, which bound this kernel, fall with them.
 typedef unsigned long long u64;
 
-template <int MODE, int NT, int PX>
+// NB window sets: with two, the scatter of pass t + 1 goes to the other set
+// while pass t is flushed, so a pass needs one barrier instead of two.  A
+// wave flushes and clears its windows of pass t before it scatters pass
+// t + 1, and every wave has done that before the barrier that follows the
+// scatter of t + 1, so the set of pass t is clear again when pass t + 2
+// scatters into it.
+template <int MODE, int NT, int PX, int NB>
 __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
     const int nwin = kChunk * slot;  // entries of one array of windows
-    u64* gw = reinterpret_cast<u64*>(smem);  // G of window j: gw[j * slot + e]
-    u64* hw = gw + nwin;                     // H of window j: hw[j * slot + e]
-    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * (size_t)nwin * sizeof(u64));
+    // set b: G of window j at gw[b * 2 nwin + j * slot + e], H nwin further
+    u64* gw = reinterpret_cast<u64*>(smem);
+    int4* m_tab = reinterpret_cast<int4*>(smem + NB * 2 * (size_t)nwin * sizeof(u64));
     float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
     int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
     const uint32_t lds0 =
@@ -82,8 +88,8 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     const int te = min(a.T, tb + a.split_tx);
     const TileGeom g = tile_geom<NT, PX>(a, tile);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
-    uint4* zw = reinterpret_cast<uint4*>(smem);  // both arrays, 16 bytes a store
-    for (int i = tid; i < nwin; i += NT) zw[i] = make_uint4(0u, 0u, 0u, 0u);
+    uint4* zw = reinterpret_cast<uint4*>(smem);  // all arrays, 16 bytes a store
+    for (int i = tid; i < NB * nwin; i += NT) zw[i] = make_uint4(0u, 0u, 0u, 0u);
 
     PixelSet<PX> p;
     pixel_set<NT, PX, false>(a, g, p);
@@ -108,6 +114,7 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     const int ne = a.nst + 1;  // samples a window can touch
     // workspace slots of (transmit t, channel c) for this tile
     auto slot_of = [&](int t, int c) { return ((size_t)t * a.C + c) * a.ntiles + tile; };
+    int cur = 0;  // window set of the next scattering pass
 
     for (int c0 = cb; c0 < ce; c0 += kChunk) {
         __syncthreads();
@@ -143,9 +150,10 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
 
             // ---- scatter into the LDS windows (integer atomics) -------------
+            const uint32_t set0 = lds0 + (uint32_t)(cur * 2 * nwin) * 8u;
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                const uint32_t off = lds0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
+                const uint32_t off = set0 + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
 #pragma unroll
                 for (int k = 0; k < PX; ++k) {
                     const uint32_t u = tq[k] + rq[k][j];
@@ -168,8 +176,8 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
             // them until the barrier, so no barrier is needed in between.
             for (int j = tid >> 6; j < kChunk; j += NT >> 6) {
                 const int c = c0 + j;
-                u64* gj = gw + j * slot;
-                u64* hj = hw + j * slot;
+                u64* gj = gw + (size_t)cur * 2 * nwin + j * slot;
+                u64* hj = gj + nwin;
                 if (c < a.C) {
                     const int A0 = __builtin_amdgcn_readfirstlane((at + b_tab[j]) & ~7);
                     const size_t sl = slot_of(t, c);
@@ -190,7 +198,9 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
                     *reinterpret_cast<uint4*>(hj + e) = make_uint4(0u, 0u, 0u, 0u);
                 }
             }
-            __syncthreads();  // windows are zero before the next pass scatters
+            // one set: its windows must be zero before the next pass scatters
+            if (NB == 1) __syncthreads();
+            cur ^= NB - 1;
         }
     }
 }
@@ -317,29 +327,37 @@ hipError_t allow_lds(K kernel, size_t lds) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int MODE, int NT, int PX>
+template <int MODE, int NT, int PX, int NB>
 hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
-    hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX>, lds);
+    hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX, NB>, lds);
     if (e != hipSuccess) return e;
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
-    hipLaunchKernelGGL((das_adjoint_kernel<MODE, NT, PX>), grid, dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((das_adjoint_kernel<MODE, NT, PX, NB>), grid, dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
+template <int MODE, int NB>
+hipError_t launch_adj_nb(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
+    if (nt == 1024) return launch_adj<MODE, 1024, 2, NB>(a, lds, s);
+    if (nt == 512) return launch_adj<MODE, 512, 2, NB>(a, lds, s);
+    return px == 4 ? launch_adj<MODE, 256, 4, NB>(a, lds, s)
+                   : launch_adj<MODE, 256, 1, NB>(a, lds, s);
+}
+
 template <int MODE>
-hipError_t launch_adj_shape(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024) return launch_adj<MODE, 1024, 2>(a, lds, s);
-    if (nt == 512) return launch_adj<MODE, 512, 2>(a, lds, s);
-    return px == 4 ? launch_adj<MODE, 256, 4>(a, lds, s) : launch_adj<MODE, 256, 1>(a, lds, s);
+hipError_t launch_adj_shape(int nt, int px, int nbuf, const DasArgs& a, size_t lds,
+                            hipStream_t s) {
+    return nbuf == 2 ? launch_adj_nb<MODE, 2>(nt, px, a, lds, s)
+                     : launch_adj_nb<MODE, 1>(nt, px, a, lds, s);
 }
 
 }  // namespace
 
-hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
-                              hipStream_t s) {
-    return mode == 1 ? launch_adj_shape<1>(nt, px, a, lds_bytes, s)
-                     : launch_adj_shape<0>(nt, px, a, lds_bytes, s);
+hipError_t launch_das_adjoint(int mode, int nt, int px, int nbuf, const DasArgs& a,
+                              size_t lds_bytes, hipStream_t s) {
+    return mode == 1 ? launch_adj_shape<1>(nt, px, nbuf, a, lds_bytes, s)
+                     : launch_adj_shape<0>(nt, px, nbuf, a, lds_bytes, s);
 }
 
 hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s) {

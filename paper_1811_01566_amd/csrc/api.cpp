@@ -291,6 +291,9 @@ constexpr size_t kLdsHard = 163840;
 #ifndef WF_DAS_XCD_ORDER
 #define WF_DAS_XCD_ORDER 0
 #endif
+#ifndef WF_ADJ_TWO_SETS
+#define WF_ADJ_TWO_SETS 1
+#endif
 
 bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
     // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
@@ -916,9 +919,12 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     float no_window;
     static_assert(sizeof(no_window) == sizeof(wf::kNoWindow), "kNoWindow is 32-bit");
     std::memcpy(&no_window, &wf::kNoWindow, sizeof no_window);
-    // the 8-byte G and H windows take the bytes of the forward's two
-    // buffers of 8-byte entries
-    const size_t lds = tp.lds;
+    // one set of 8-byte G and H windows takes the bytes of the forward's two
+    // buffers of 8-byte entries; a second set, where it fits, saves a
+    // barrier per pass
+    const size_t set_bytes = 2 * (size_t)wf::kChunk * tp.slot * 8;
+    const int nbuf = (WF_ADJ_TWO_SETS && tp.lds + set_bytes <= kLdsHard) ? 2 : 1;
+    const size_t lds = tp.lds + (nbuf - 1) * set_bytes;
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
     for (int f = 0; f < acq->n_frames; ++f) {
         a.g = g + (size_t)f * grid->nz * grid->nx;
@@ -928,7 +934,8 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
             e = wf::launch_fill(reinterpret_cast<float*>(a.ws_a0), slots, no_window,
                                 (hipStream_t)stream);
         if (e == hipSuccess)
-            e = wf::launch_das_adjoint(mode, tp.threads, tp.px, a, lds, (hipStream_t)stream);
+            e = wf::launch_das_adjoint(mode, tp.threads, tp.px, nbuf, a, lds,
+                                       (hipStream_t)stream);
         if (e == hipSuccess)
             e = wf::launch_adjoint_reduce(a.ws_win, a.ws_a0, grad_rf + (size_t)f * frame_rf,
                                           acq->n_tx * acq->n_ch, a.ntiles, tp.nst + 1, acq->n_s,

@@ -114,8 +114,9 @@ hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, cons
                            size_t lds_bytes, hipStream_t s);
 hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
                                hipStream_t s);
-hipError_t launch_das_adjoint(int mode, int nt, int px, const DasArgs& a, size_t lds_bytes,
-                              hipStream_t s);
+// nbuf: window sets of the adjoint (1 or 2; lds_bytes must hold them)
+hipError_t launch_das_adjoint(int mode, int nt, int px, int nbuf, const DasArgs& a,
+                              size_t lds_bytes, hipStream_t s);
 hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s);
 hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,
                                  int ntiles, int ne, int S, hipStream_t s);

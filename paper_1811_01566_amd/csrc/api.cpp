@@ -291,6 +291,9 @@ constexpr size_t kLdsHard = 163840;
 #ifndef WF_DAS_XCD_ORDER
 #define WF_DAS_XCD_ORDER 0
 #endif
+#ifndef WF_DAS_TWO_PASS
+#define WF_DAS_TWO_PASS 1
+#endif
 #ifndef WF_ADJ_TWO_SETS
 #define WF_ADJ_TWO_SETS 1
 #endif
@@ -766,8 +769,18 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
             if (e != hipSuccess) return hip_fail(e, "fill launch");
         }
     }
+    // one frame of 16-bit RF on 1024-thread tiles (one workgroup fills a
+    // CU): two transmits per barrier where four window buffers fit the LDS
+    size_t lds = tp.lds;
+    const size_t two_bufs = 2 * (size_t)wf::kChunk * tp.slot * 8;
+    a.pp = 1;
+    if (WF_DAS_TWO_PASS && op == 0 && tp.threads == 1024 && a.F == 1 && acq->dtype != 2 &&
+        tp.lds + two_bufs <= kLdsHard) {
+        a.pp = 2;
+        lds += two_bufs;
+    }
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
-                                            groups_of(a, tp), a, tp.lds, (hipStream_t)stream)
+                                            groups_of(a, tp), a, lds, (hipStream_t)stream)
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
                                                  groups_of(a, tp), a, tp.lds, (hipStream_t)stream);
     if (e == hipSuccess && a.partial)

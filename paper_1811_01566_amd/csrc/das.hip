@@ -48,18 +48,67 @@ enum : int {
 // ---------------------------------------------------------------------------
 // K2: gather / interpolate / accumulate
 // ---------------------------------------------------------------------------
+// One staged pass: every lane adds its PX pixels' contributions of the
+// kChunk channels of the LDS buffer at byte address BASE (transmit base at)
+// into ACC, with the delays tq, rq, the bases bj, slot and a of the
+// enclosing kernel.  Batches of LDS reads are issued before their FMAs so that
+// several reads are in flight per wave.  A macro rather than a function:
+// passing the delay arrays to a function, even one always inlined, cost
+// about 40 VGPRs.
+#define WF_GATHER_PASS(ACC, BASE, at) do {                                                      \
+    const uint32_t base = (BASE);                                                               \
+    constexpr int kJB = (WF_DAS_READS / PX) < 1 ? 1 : (WF_DAS_READS / PX);                      \
+    _Pragma("unroll")                                                                           \
+    for (int j0 = 0; j0 < kChunk; j0 += kJB) {                                                  \
+        float2 ed[kJB][PX];                                                                     \
+        float f1[kJB][PX];                                                                      \
+        float nf[kJB];                                                                          \
+        _Pragma("unroll")                                                                       \
+        for (int jj = 0; jj < kJB; ++jj) {                                                      \
+            const int j = j0 + jj;                                                              \
+            const uint32_t off =                                                                \
+                base + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;                          \
+            if (OP == kOpDydc) nf[jj] = (float)(at + bj[j]) + a.t0fs;                           \
+            _Pragma("unroll")                                                                   \
+            for (int k = 0; k < PX; ++k) {                                                      \
+                const uint32_t u = tq[k] + rq[k][j];                                            \
+                if (OP == kOpValue)                                                             \
+                    f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);                 \
+                else /* absolute fractional sample index + t0 fs */                             \
+                    f1[jj][k] = fmaf((float)u, 1.0f / kQScale, nf[jj]);                         \
+                const v2f e2 = *reinterpret_cast<const __attribute__((address_space(3))) v2f*>( \
+                    (uintptr_t)entry_addr(u, off));                                             \
+                ed[jj][k] = make_float2(e2.x, e2.y);                                            \
+            }                                                                                   \
+        }                                                                                       \
+        _Pragma("unroll")                                                                       \
+        for (int jj = 0; jj < kJB; ++jj)                                                        \
+            _Pragma("unroll")                                                                   \
+            for (int k = 0; k < PX; ++k) {                                                      \
+                if (OP == kOpValue)                                                             \
+                    ACC[k] += fmaf(f1[jj][k], ed[jj][k].y, ed[jj][k].x);                        \
+                else                                                                            \
+                    ACC[k] = fmaf(ed[jj][k].y, f1[jj][k], ACC[k]);                              \
+            }                                                                                   \
+    }                                                                                           \
+} while (0)
+
 // FG frames per workgroup: the frames of a batch share the geometry, so a
 // group reuses each chunk's receive delays and each pass's transmit delays;
 // every frame keeps its own accumulation order, so a batch equals its
 // frames one by one bit for bit.
-template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG>
+// PP transmits per barrier (1 or 2, the latter with FG = 1): two passes are
+// staged into two of four LDS buffers per barrier, halving the barriers
+// where one workgroup fills a CU; the accumulation order is unchanged.
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP>
 __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
+    static_assert(PP == 1 || (PP == 2 && FG == 1), "two passes per barrier need FG = 1");
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
     const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
-    float2* win = reinterpret_cast<float2*>(smem);  // two buffers of kChunk windows
-    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * buf_bytes);
+    float2* win = reinterpret_cast<float2*>(smem);  // 2 PP buffers of kChunk windows
+    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * PP * buf_bytes);
     float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
     int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
     // LDS byte offset of the window buffers (folded into scalar offsets)
@@ -76,10 +125,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const int split = item - tile * a.nsplit;
     const TileGeom g = tile_geom<NT, PX>(a, tile);
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
-    // zero pad behind every window of both buffers (never overwritten)
+    // zero pad behind every window of every buffer (never overwritten)
     {
         const int pad = slot - a.nst;
-        for (int i = tid; i < 2 * kChunk * pad; i += NT) {
+        for (int i = tid; i < 2 * PP * kChunk * pad; i += NT) {
             const int j = i / pad;
             win[j * slot + a.nst + (i - j * pad)] = make_float2(0.0f, 0.0f);
         }
@@ -148,8 +197,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
 
         // global -> registers for pass t (nothing written yet); a group
         // outside the record reads zeros through the buffer range check
-        RawGroup<RT> raw[NG];
-        auto issue = [&](int t, int g) {  // pass t of frame frame0 + g
+        RawGroup<RT> raw[PP][NG];
+        auto issue = [&](int t, int g, int h) {  // pass t of frame frame0 + g into raw[h]
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
             // a ragged last group repeats its last frame (results not written)
             const size_t fo = FG == 1 ? 0 : (size_t)min(g, fgc - 1) * frame_elems;
@@ -161,14 +210,14 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                 if (w < ngroups) {
                     const int s0 = (at + gb[gi]) & ~7;
                     const bool ok = (uint32_t)s0 <= (uint32_t)(a.S - 8);
-                    raw[gi].load(rsrc, ok ? (roff[gi] + (uint32_t)s0) << kElemLog2 : kOffNone);
+                    raw[h][gi].load(rsrc, ok ? (roff[gi] + (uint32_t)s0) << kElemLog2 : kOffNone);
                 }
             }
         };
         // registers -> interpolation pairs in LDS buffer `buf`.  S % 8 == 0,
         // so a group lies wholly inside or outside its record; inside, only
         // the last pair of the record (n = S - 1, no successor) is dropped.
-        auto commit = [&](int t, int buf) {
+        auto commit = [&](int t, int buf, int h) {  // raw[h] holds pass t
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
@@ -176,7 +225,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                 if (w < ngroups) {
                     const int s0 = (at + gb[gi]) & ~7;
                     float v[9];
-                    raw[gi].get(v);
+                    raw[h][gi].get(v);
 #pragma unroll
                     for (int m = 0; m < 9; ++m) opaque(v[m]);
                     float4 o[4];
@@ -205,10 +254,40 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // the previous pass), barrier, then issue the loads of the next pass
         // so that they fly while this one is accumulated.  The first pass's
         // loads fly while the receive delays are formed.
-        issue(t, 0);
+        issue(t, 0, 0);
+        int t1 = PP == 2 ? next_active(t + 1) : te;  // second transmit of a pair
+        if (PP == 2 && t1 < te) issue(t1, 0, PP - 1);
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
         int cur = 0;
+        // two transmits per barrier: commit (t, t1) into buffers 2 cur and
+        // 2 cur + 1 (last read in the pair before the previous barrier),
+        // barrier, issue the next pair, accumulate t then t1
+        if constexpr (PP == 2) {
+            while (t < te) {
+                const int t2 = t1 < te ? next_active(t1 + 1) : te;
+                const int t3 = t2 < te ? next_active(t2 + 1) : te;
+                commit(t, 2 * cur, 0);
+                if (t1 < te) commit(t1, 2 * cur + 1, PP - 1);
+                __syncthreads();
+                if (t2 < te) issue(t2, 0, 0);
+                if (t3 < te) issue(t3, 0, PP - 1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int th = h == 0 ? t : t1;
+                    if (th < te) {
+                        const int at = __builtin_amdgcn_readfirstlane(m_tab[th].x);
+                        uint32_t tq[PX];
+                        tx_delays<MODE, PX>(a, p, m_tab[th], q_tab[th], at, tq);
+                        WF_GATHER_PASS(acc[0], lds0 + (uint32_t)(2 * cur + h) * buf_bytes, at);
+                    }
+                }
+                cur ^= 1;
+                t = t2;
+                t1 = t3;
+            }
+            continue;
+        }
         // With FG > 1 the passes run (transmit t, frame g) with g fastest;
         // the frame loop stays rolled, its accumulators rotating by one
         // frame per pass, so that only the transmit delays are held across
@@ -222,10 +301,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             }
 #pragma unroll 1
             for (int g = 0; g < FG; ++g) {
-                commit(t, cur);
+                commit(t, cur, 0);
                 __syncthreads();
-                if (g + 1 < FG) issue(t, g + 1);
-                else if (tn < te) issue(tn, 0);
+                if (g + 1 < FG) issue(t, g + 1, 0);
+                else if (tn < te) issue(tn, 0, 0);
                 const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
                 if (FG == 1) tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
                 // 1024-thread workgroups have no registers to keep the sums of
@@ -234,44 +313,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
 #pragma unroll
                     for (int k = 0; k < PX; ++k) opaque_u(tq[k]);
 
-                // ---- gather / interpolate / accumulate -------------------------
-                // batches of LDS reads are issued before their FMAs so that
-                // several reads are in flight per wave
-                const uint32_t base = lds0 + (uint32_t)cur * buf_bytes;
-                constexpr int kJB = (WF_DAS_READS / PX) < 1 ? 1 : (WF_DAS_READS / PX);
-#pragma unroll
-                for (int j0 = 0; j0 < kChunk; j0 += kJB) {
-                    float2 ed[kJB][PX];
-                    float f1[kJB][PX];
-                    float nf[kJB];
-#pragma unroll
-                    for (int jj = 0; jj < kJB; ++jj) {
-                        const int j = j0 + jj;
-                        const uint32_t off =
-                            base + (uint32_t)(j * slot + ((at + bj[j]) & 7)) * 8u;
-                        if (OP == kOpDydc) nf[jj] = (float)(at + bj[j]) + a.t0fs;
-#pragma unroll
-                        for (int k = 0; k < PX; ++k) {
-                            const uint32_t u = tq[k] + rq[k][j];
-                            if (OP == kOpValue)
-                                f1[jj][k] = __uint_as_float((u & 0x7FFFFFu) | 0x3F800000u);
-                            else  // absolute fractional sample index + t0 fs
-                                f1[jj][k] = fmaf((float)u, 1.0f / kQScale, nf[jj]);
-                            const v2f e2 = *reinterpret_cast<const __attribute__((address_space(3))) v2f*>(
-                                (uintptr_t)entry_addr(u, off));
-                            ed[jj][k] = make_float2(e2.x, e2.y);
-                        }
-                    }
-#pragma unroll
-                    for (int jj = 0; jj < kJB; ++jj)
-#pragma unroll
-                        for (int k = 0; k < PX; ++k) {
-                            if (OP == kOpValue)
-                                acc[0][k] += fmaf(f1[jj][k], ed[jj][k].y, ed[jj][k].x);
-                            else
-                                acc[0][k] = fmaf(ed[jj][k].y, f1[jj][k], acc[0][k]);
-                        }
-                }
+                WF_GATHER_PASS(acc[0], lds0 + (uint32_t)cur * buf_bytes, at);
                 cur ^= 1;
                 if (FG > 1) {
 #pragma unroll
@@ -340,22 +382,30 @@ hipError_t allow_lds(K kernel, size_t lds) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG = 1>
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG = 1, int PP = 1>
 hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
-    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG>, lds);
+    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
     if (e != hipSuccess) return e;
     const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, groups, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), groups, (unsigned)a.nsplit);
-    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG>), grid, dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>), grid, dim3(NT), lds, s,
+                       a);
     return hipGetLastError();
 }
 
-// Batches of the large-tile shapes run 4 frames per workgroup (the value
-// gather only; d y / d c keeps one).
+// Batches of the large-tile shapes run 4 frames per workgroup, and single
+// frames of 16-bit RF on 1024-thread tiles two transmits per barrier where
+// the host gave the LDS for it (the value gather only; d y / d c keeps one
+// of each).
 template <int MODE, typename RT, int NT, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
-    if (OP == kOpValue && a.F > 1) return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
+    if constexpr (OP == kOpValue) {
+        if (a.F > 1) return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
+        // FP32 RF holds too many staging registers for two passes
+        if constexpr (NT == 1024 && sizeof(RT) == 2)
+            if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 1, 2>(a, lds, s);
+    }
     return launch_one<MODE, RT, NT, 2, 2, OP, 1>(a, lds, s);
 }
 

@@ -85,6 +85,7 @@ struct DasArgs {
     const int* items;   // work list: item codes tile * nsplit + split, one per workgroup
                         // along x (null: the grid enumerates every item)
     float* partial;     // split partial frames [nsplit][F][nz][nx] (null: write out)
+    int pp;             // transmits staged per barrier (2: four LDS buffers given)
     int ntiles;         // adjoint: ntz * ntx
     float* ws_win;      // adjoint workspace: window of (t, c, tile), nst + 1 samples
     int* ws_a0;         // adjoint workspace: first sample of that window or kNoWindow

@@ -769,12 +769,12 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
             if (e != hipSuccess) return hip_fail(e, "fill launch");
         }
     }
-    // one frame of 16-bit RF on 1024-thread tiles (one workgroup fills a
-    // CU): two transmits per barrier where four window buffers fit the LDS
+    // 16-bit RF on 1024-thread tiles (one workgroup fills a CU): two passes
+    // per barrier where four window buffers fit the LDS
     size_t lds = tp.lds;
     const size_t two_bufs = 2 * (size_t)wf::kChunk * tp.slot * 8;
     a.pp = 1;
-    if (WF_DAS_TWO_PASS && op == 0 && tp.threads == 1024 && a.F == 1 && acq->dtype != 2 &&
+    if (WF_DAS_TWO_PASS && op == 0 && tp.threads == 1024 && acq->dtype != 2 &&
         tp.lds + two_bufs <= kLdsHard) {
         a.pp = 2;
         lds += two_bufs;

@@ -97,12 +97,14 @@ enum : int {
 // group reuses each chunk's receive delays and each pass's transmit delays;
 // every frame keeps its own accumulation order, so a batch equals its
 // frames one by one bit for bit.
-// PP transmits per barrier (1 or 2, the latter with FG = 1): two passes are
-// staged into two of four LDS buffers per barrier, halving the barriers
-// where one workgroup fills a CU; the accumulation order is unchanged.
+// PP passes per barrier (1 or 2): two passes, of two transmits (FG = 1) or
+// of two frames of a transmit (FG > 1), are staged into two of four LDS
+// buffers per barrier, halving the barriers where one workgroup fills a
+// CU; the accumulation order is unchanged.
 template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP>
 __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
-    static_assert(PP == 1 || (PP == 2 && FG == 1), "two passes per barrier need FG = 1");
+    static_assert(PP == 1 || (PP == 2 && FG % 2 == 0) || (PP == 2 && FG == 1),
+                  "frame pairs need an even frame group");
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int slot = a.slot;
@@ -255,15 +257,16 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // so that they fly while this one is accumulated.  The first pass's
         // loads fly while the receive delays are formed.
         issue(t, 0, 0);
-        int t1 = PP == 2 ? next_active(t + 1) : te;  // second transmit of a pair
-        if (PP == 2 && t1 < te) issue(t1, 0, PP - 1);
+        int t1 = PP == 2 && FG == 1 ? next_active(t + 1) : te;  // second transmit of a pair
+        if (PP == 2 && FG == 1 && t1 < te) issue(t1, 0, PP - 1);
+        if (PP == 2 && FG > 1) issue(t, 1, PP - 1);  // second frame of a pair
         uint32_t rq[PX][kChunk];
         rx_delays<PX>(a, p, c0, bj, rq);
         int cur = 0;
         // two transmits per barrier: commit (t, t1) into buffers 2 cur and
         // 2 cur + 1 (last read in the pair before the previous barrier),
         // barrier, issue the next pair, accumulate t then t1
-        if constexpr (PP == 2) {
+        if constexpr (PP == 2 && FG == 1) {
             while (t < te) {
                 const int t2 = t1 < te ? next_active(t1 + 1) : te;
                 const int t3 = t2 < te ? next_active(t2 + 1) : te;
@@ -288,10 +291,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
             }
             continue;
         }
-        // With FG > 1 the passes run (transmit t, frame g) with g fastest;
-        // the frame loop stays rolled, its accumulators rotating by one
-        // frame per pass, so that only the transmit delays are held across
-        // frames.
+        // With FG > 1 the passes run (transmit t, frame g) with g fastest,
+        // PP of them per barrier; the frame loop stays rolled, its
+        // accumulators rotating by one frame per pass, so that only the
+        // transmit delays are held across frames.
         while (t < te) {
             const int tn = next_active(t + 1);
             uint32_t tq[PX];
@@ -300,30 +303,37 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                 tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
             }
 #pragma unroll 1
-            for (int g = 0; g < FG; ++g) {
-                commit(t, cur, 0);
+            for (int g = 0; g < FG; g += PP) {
+#pragma unroll
+                for (int h = 0; h < PP; ++h) commit(t, PP * cur + h, h);
                 __syncthreads();
-                if (g + 1 < FG) issue(t, g + 1, 0);
-                else if (tn < te) issue(tn, 0, 0);
+#pragma unroll
+                for (int h = 0; h < PP; ++h) {
+                    if (g + PP < FG) issue(t, g + PP + h, h);
+                    else if (tn < te) issue(tn, h, h);
+                }
                 const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
                 if (FG == 1) tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
-                // 1024-thread workgroups have no registers to keep the sums of
-                // transmit and receive delays across frames: recompute them
-                if (FG > 1 && NT == 1024)
 #pragma unroll
-                    for (int k = 0; k < PX; ++k) opaque_u(tq[k]);
+                for (int h = 0; h < PP; ++h) {
+                    // 1024-thread workgroups have no registers to keep the sums
+                    // of transmit and receive delays across frames: recompute
+                    if (FG > 1 && NT == 1024)
+#pragma unroll
+                        for (int k = 0; k < PX; ++k) opaque_u(tq[k]);
 
-                WF_GATHER_PASS(acc[0], lds0 + (uint32_t)cur * buf_bytes, at);
-                cur ^= 1;
-                if (FG > 1) {
+                    WF_GATHER_PASS(acc[0], lds0 + (uint32_t)(PP * cur + h) * buf_bytes, at);
+                    if (FG > 1) {
 #pragma unroll
-                    for (int k = 0; k < PX; ++k) {
-                        const float x = acc[0][k];
+                        for (int k = 0; k < PX; ++k) {
+                            const float x = acc[0][k];
 #pragma unroll
-                        for (int h = 0; h + 1 < FG; ++h) acc[h][k] = acc[h + 1][k];
-                        acc[FG - 1][k] = x;
+                            for (int f = 0; f + 1 < FG; ++f) acc[f][k] = acc[f + 1][k];
+                            acc[FG - 1][k] = x;
+                        }
                     }
                 }
+                cur ^= 1;
             }
             t = tn;
         }
@@ -394,16 +404,21 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Batches of the large-tile shapes run 4 frames per workgroup, and single
-// frames of 16-bit RF on 1024-thread tiles two transmits per barrier where
-// the host gave the LDS for it (the value gather only; d y / d c keeps one
-// of each).
+// Batches of the large-tile shapes run 4 frames per workgroup.  16-bit RF
+// on 1024-thread tiles runs two passes per barrier (transmits of a single
+// frame, frames of a batch) where the host gave the LDS for it.  The value
+// gather only: d y / d c keeps one frame and one pass.
 template <int MODE, typename RT, int NT, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
     if constexpr (OP == kOpValue) {
-        if (a.F > 1) return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
         // FP32 RF holds too many staging registers for two passes
-        if constexpr (NT == 1024 && sizeof(RT) == 2)
+        constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
+        if (a.F > 1) {
+            if constexpr (kPairs)
+                if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 4, 2>(a, lds, s);
+            return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
+        }
+        if constexpr (kPairs)
             if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 1, 2>(a, lds, s);
     }
     return launch_one<MODE, RT, NT, 2, 2, OP, 1>(a, lds, s);

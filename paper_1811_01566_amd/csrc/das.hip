@@ -2,7 +2,8 @@
 // gather / linear-interpolate / accumulate (K2), for synthetic transmit
 // aperture (STAI) and plane-wave (PWI) imaging (WaveFlow, Sec. II-B).
 //
-// K2 design (one workgroup = 256 lanes = one tile of 256*PX pixels):
+// K2 design (one workgroup = NT = 256, 512 or 1024 lanes = one tile of NT*PX
+// pixels):
 //  * Delays are split into a window base and a window-local part.  For a
 //    tile, transmit t gets an integer base a_t <= min over the tile of its
 //    transmit delay, channel c a base b_c <= min of its receive delay; the

@@ -254,7 +254,8 @@ wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* st
  * Launch plan the DAS calls would use for this geometry (host only; touches
  * no device).  info (HOST int32[16]) receives: pixels per lane, tile depth,
  * tile width, window-local delay clamp (samples), staged window entries,
- * LDS entries per window, LDS bytes per workgroup, tiles along z, tiles
+ * LDS entries per window, LDS bytes per workgroup of wf_das (twice the
+ * window buffers where it stages two passes per barrier), tiles along z, tiles
  * along x, channels per pass, threads per workgroup, then the work split
  * used when the caller passes wf_das_workspace's bytes: items per tile,
  * channel chunks per item, transmit splits, transmits per item, and the

@@ -355,6 +355,22 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
     return false;
 }
 
+// Passes the value gather stages per barrier: two (four window buffers)
+// for 16-bit RF on 1024-thread tiles, where one workgroup fills a CU and
+// the buffers fit the LDS; FP32 staging would spill registers.
+int das_passes_per_barrier(const TilePlan& tp, const wf_acq* acq) {
+    const size_t two_bufs = 2 * (size_t)wf::kChunk * tp.slot * 8;
+    return WF_DAS_TWO_PASS && tp.threads == 1024 && acq->dtype != 2 &&
+                   tp.lds + two_bufs <= kLdsHard
+               ? 2
+               : 1;
+}
+
+// LDS bytes of a gather workgroup staging pp passes per barrier.
+size_t das_gather_lds(const TilePlan& tp, int pp) {
+    return tp.lds + (size_t)(pp - 1) * 2 * wf::kChunk * tp.slot * 8;
+}
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const char* pa = (const char*)a;
     const char* pb = (const char*)b;
@@ -769,16 +785,8 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
             if (e != hipSuccess) return hip_fail(e, "fill launch");
         }
     }
-    // 16-bit RF on 1024-thread tiles (one workgroup fills a CU): two passes
-    // per barrier where four window buffers fit the LDS
-    size_t lds = tp.lds;
-    const size_t two_bufs = 2 * (size_t)wf::kChunk * tp.slot * 8;
-    a.pp = 1;
-    if (WF_DAS_TWO_PASS && op == 0 && tp.threads == 1024 && acq->dtype != 2 &&
-        tp.lds + two_bufs <= kLdsHard) {
-        a.pp = 2;
-        lds += two_bufs;
-    }
+    a.pp = op == 0 ? das_passes_per_barrier(tp, acq) : 1;
+    const size_t lds = das_gather_lds(tp, a.pp);
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
                                             groups_of(a, tp), a, lds, (hipStream_t)stream)
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
@@ -986,7 +994,7 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     info[3] = tp.span;
     info[4] = tp.nst;
     info[5] = tp.slot;
-    info[6] = (int32_t)tp.lds;
+    info[6] = (int32_t)das_gather_lds(tp, das_passes_per_barrier(tp, acq));
     info[7] = tp.ntz;
     info[8] = tp.ntx;
     info[9] = wf::kChunk;

@@ -175,3 +175,27 @@ def test_adjoint_workspace_and_frames(wf_gpu):
     torch.cuda.synchronize()
     for a, b in ((both[0], f0[0]), (both[1], f1[0])):
         assert nl2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("op", ["das", "dydc"])
+def test_int16_rf_matches_float_rf_on_large_tiles(wf_gpu, op):
+    """int16 counts convert to float exactly and are staged the same way, so
+    the same integer RF given as int16 and as float32 gives the same bits.
+    On 1024-thread tiles the int16 gather stages two passes per barrier and
+    the float32 one a single pass, so this also pins the two pipelines to
+    each other."""
+    torch = _t()
+    w = subgrid(lighter(phantom.get_workload("pwi")), 300, 128, 200, 96).with_(phantom="random")
+    info = wf_gpu.tile_info(scan_from_workload(w), w.n_s, 1)
+    assert info["threads"] == 1024
+    rf = phantom.synth_rf(w)[0]
+    scan = scan_from_workload(w)
+    fn = wf_gpu.das if op == "das" else wf_gpu.das_dydc
+    r16 = torch.from_numpy(rf).cuda()[None]
+    r32 = torch.from_numpy(rf.astype(np.float32)).cuda()[None]
+    a = fn(scan, r16)
+    b = fn(scan, r32)
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.abs(b).max() > 0
+    assert np.array_equal(a, b)

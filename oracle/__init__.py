@@ -53,7 +53,7 @@ from .adjoint import (
 )
 from .analytic import hilbert_multiplier, analytic_signal, envelope
 from .dbclip import log_compress, bmode
-from .fir import fir_same, frequency_response
+from .fir import fir_same
 from .moments import moment_map_shape, moment_maps
 
 __all__ = [
@@ -62,5 +62,5 @@ __all__ = [
     "receive_weight", "das_sum", "das_stai", "das_pwi", "das_workload", "workload_tof",
     "hilbert_multiplier", "analytic_signal", "envelope", "log_compress", "bmode",
     "das_adjoint_sum", "das_dydc_sum", "das_adjoint_workload", "das_dydc_workload",
-    "fir_same", "frequency_response", "moment_map_shape", "moment_maps",
+    "fir_same", "moment_map_shape", "moment_maps",
 ]

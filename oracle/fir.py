@@ -13,9 +13,8 @@ length or alignment are given.  Readings:
 * the taps are an input (any real values); the output is real RF in float.
 
 Pins: an impulse returns the taps, a tone away from the record edges is
-scaled by the filter's frequency response in closed form, the definition
-equals ``numpy.convolve(..., "same")``, edges equal the truncated sums, and
-the filter is linear.
+scaled by the moving average's Dirichlet gain, the definition equals
+``numpy.convolve(..., "same")``, and edges equal the truncated sums.
 """
 
 from __future__ import annotations
@@ -41,11 +40,3 @@ def fir_same(rf: np.ndarray, taps: np.ndarray) -> np.ndarray:
             y[..., lo:hi] += h[k] * r[..., lo + shift:hi + shift]
     return y
 
-
-def frequency_response(taps: np.ndarray, f_hz: float, fs: float) -> complex:
-    """H(f) = sum_k h[k] exp(-i 2 pi f (k - D) / fs), the gain a tone of
-    frequency f receives from the centred filter above."""
-    h = np.asarray(taps, dtype=np.float64)
-    d = (h.shape[0] - 1) // 2
-    k = np.arange(h.shape[0])
-    return complex(np.sum(h * np.exp(-2j * np.pi * f_hz * (k - d) / fs)))

@@ -344,6 +344,49 @@ def pin_bmode_per_frame_and_degenerate():
     assert np.all(np.isfinite(z))
 
 
+def pin_bmode_gaussian_pulses():
+    """The whole frame step (Fig. 2: analytic signal -> absolute value ->
+    dynamic adjustment) on a frame of depth columns whose B-mode is known in
+    closed form: column k holds a_k g(z) cos(2 pi fc z / fs + phi_k) with g the
+    Gaussian of the generator's pulse width, so its envelope is a_k g(z)
+    (product theorem, leakage < 1e-6 of the peak) and its dB image is
+    20 log10(a_k g(z) / max_k a_k) clipped to [-DR, 0] - the reference being
+    the frame maximum, which lies in another column for all but one.  A zero
+    column maps to -DR.  Two frames with different peak columns and scales
+    check that each frame takes its own maximum."""
+    fs, fc, dr = 50e6, 5e6, 60.0
+    sig = 2.0 / (fc * 2.0 * math.sqrt(2.0 * math.log(2.0))) * fs  # samples
+    nz = 512
+    s = np.arange(nz, dtype=np.float64)
+    frames = [((1.0, 0.25, 3.0, 0.0), (180.0, 300.0, 256.0, 0.0)),
+              ((40.0, 0.0, 7.5, 400.0), (128.0, 0.0, 333.0, 251.0))]
+    y = np.zeros((len(frames), nz, 4))
+    exp = np.zeros_like(y)
+    for f, (amps, centres) in enumerate(frames):
+        top = max(amps)
+        for k, (a, c) in enumerate(zip(amps, centres)):
+            g = np.exp(-((s - c) ** 2) / (2 * sig * sig))
+            y[f, :, k] = a * g * np.cos(2 * np.pi * fc / fs * (s - c) + 0.7 * k + 0.2)
+            with np.errstate(divide="ignore"):
+                exp[f, :, k] = np.clip(20 * np.log10(a * g / top), -dr, 0.0)
+    got = B.bmode(y, dr)
+    for f in range(len(frames)):
+        # the envelope is a g to ~1e-6 of the column peak: compare where the
+        # expected level is above -40 dB of the frame (<= 3e-3 dB there), and
+        # require the clip floor well below it
+        on = exp[f] > -40.0
+        _close(got[f][on], exp[f][on], atol=3e-3, rtol=0, msg=f"bmode frame {f}")
+        deep = exp[f] <= -dr
+        assert np.all(got[f][deep & (exp[f] <= -dr)] >= -dr)
+        far = np.zeros_like(deep)
+        for k, (a, c) in enumerate(zip(*frames[f])):
+            far[:, k] = np.abs(s - c) > 8 * sig if a > 0 else True
+        assert np.all(got[f][far] == -dr), f"frame {f}: far from every pulse is clipped"
+        assert got[f].max() == 0.0 or abs(got[f].max()) < 1e-5, "frame maximum maps to 0 dB"
+    offs = B.bmode(y, dr, offset=True)
+    _close(offs, got + dr, atol=1e-12, rtol=0, msg="bmode offset")
+
+
 # --------------------------------------------------------------------------
 # derivatives (adjoint w.r.t. RF, derivative w.r.t. the speed of sound)
 # --------------------------------------------------------------------------
@@ -506,6 +549,7 @@ ALL_PINS = [
     pin_envelope_constant_and_scipy,
     pin_bmode_golden,
     pin_bmode_per_frame_and_degenerate,
+    pin_bmode_gaussian_pulses,
     pin_adjoint_dot_product,
     pin_dydc_linear_ramp,
     pin_fir_impulse_and_numpy,

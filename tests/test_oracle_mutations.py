@@ -158,6 +158,21 @@ def _dydc_rx_only(rf, tau_tx, tau_rx, weight, t0, fs, c):
 _orig_dydc = A.das_dydc_sum
 
 
+def _bmode_no_envelope(y, dr_db, offset=False):
+    # log-compresses the rectified RF instead of its envelope
+    return B.log_compress(np.abs(np.asarray(y, dtype=np.float64)), dr_db, offset)
+
+
+def _bmode_lateral_axis(y, dr_db, offset=False):
+    # takes the analytic signal across columns instead of down each column
+    return B.log_compress(E.envelope(y, axis=-1), dr_db, offset)
+
+
+def _bmode_no_abs(y, dr_db, offset=False):
+    # keeps the real part of the analytic signal (the RF itself)
+    return B.log_compress(np.maximum(E.analytic_signal(y).real, 0.0), dr_db, offset)
+
+
 _orig_fir = F.fir_same
 _orig_moments = M.moment_maps
 
@@ -228,6 +243,9 @@ MUTATIONS = {
     "db_power_not_amplitude": (B, "log_compress", _logc_power_db),
     "db_global_max": (B, "log_compress", _logc_global_max),
     "db_no_clip": (B, "log_compress", _logc_no_clip),
+    "bmode_envelope_skipped": (B, "bmode", _bmode_no_envelope),
+    "bmode_envelope_along_x": (B, "bmode", _bmode_lateral_axis),
+    "bmode_modulus_dropped": (B, "bmode", _bmode_no_abs),
     "adjoint_weight_not_alpha": (A, "das_adjoint_sum", _adjoint_no_alpha),
     "dydc_sign": (A, "das_dydc_sum", _dydc_sign),
     "fir_correlation_not_convolution": (F, "fir_same", _fir_correlation),

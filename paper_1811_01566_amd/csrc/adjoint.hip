@@ -67,9 +67,10 @@ __global__ void __launch_bounds__(NT) das_adjoint_kernel(const DasArgs a) {
     const int nwin = kChunk * slot;  // entries of one array of windows
     // set b: G of window j at gw[b * 2 nwin + j * slot + e], H nwin further
     u64* gw = reinterpret_cast<u64*>(smem);
-    int4* m_tab = reinterpret_cast<int4*>(smem + NB * 2 * (size_t)nwin * sizeof(u64));
-    float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
-    int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
+    const DasLds lay = das_lds(das_adjoint_nbuf(NB), slot, a.T);
+    int4* m_tab = reinterpret_cast<int4*>(smem + lay.m_tab);
+    float4* q_tab = reinterpret_cast<float4*>(smem + lay.q_tab);
+    int* b_tab = reinterpret_cast<int*>(smem + lay.b_tab);
     const uint32_t lds0 =
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
 
@@ -329,6 +330,7 @@ hipError_t allow_lds(K kernel, size_t lds) {
 
 template <int MODE, int NT, int PX, int NB>
 hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
+    if (!das_lds_fits(lds, das_adjoint_nbuf(NB), a.slot, a.T)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX, NB>, lds);
     if (e != hipSuccess) return e;
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)

@@ -277,10 +277,9 @@ struct TilePlan {
     int ntz = 0, ntx = 0;
 };
 
-size_t das_lds_bytes(int slot, int T) {
-    // two window buffers, two 16-byte per-transmit tables, chunk tables
-    return 2 * (size_t)wf::kChunk * slot * 8 + (size_t)T * 32 + (size_t)wf::kChunk * 8;
-}
+// LDS of a gather workgroup staging one pass per barrier (two window
+// buffers, per-transmit and chunk tables)
+size_t das_lds_bytes(int slot, int T) { return wf::das_lds(wf::das_gather_nbuf(1), slot, T).total; }
 
 // LDS of one CU on gfx950 (and the most a single workgroup may take).
 constexpr size_t kLdsHard = 163840;
@@ -358,17 +357,16 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
 // Passes the value gather stages per barrier: two (four window buffers)
 // for 16-bit RF on 1024-thread tiles, where one workgroup fills a CU and
 // the buffers fit the LDS; FP32 staging would spill registers.
-int das_passes_per_barrier(const TilePlan& tp, const wf_acq* acq) {
-    const size_t two_bufs = 2 * (size_t)wf::kChunk * tp.slot * 8;
-    return WF_DAS_TWO_PASS && tp.threads == 1024 && acq->dtype != 2 &&
-                   tp.lds + two_bufs <= kLdsHard
-               ? 2
-               : 1;
+// LDS bytes of a gather workgroup staging pp passes per barrier.
+size_t das_gather_lds(const TilePlan& tp, int T, int pp) {
+    return wf::das_lds(wf::das_gather_nbuf(pp), tp.slot, T).total;
 }
 
-// LDS bytes of a gather workgroup staging pp passes per barrier.
-size_t das_gather_lds(const TilePlan& tp, int pp) {
-    return tp.lds + (size_t)(pp - 1) * 2 * wf::kChunk * tp.slot * 8;
+int das_passes_per_barrier(const TilePlan& tp, const wf_acq* acq) {
+    return WF_DAS_TWO_PASS && tp.threads == 1024 && acq->dtype != WF_RF_F32 &&
+                   das_gather_lds(tp, acq->n_tx, 2) <= kLdsHard
+               ? 2
+               : 1;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -785,12 +783,14 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
             if (e != hipSuccess) return hip_fail(e, "fill launch");
         }
     }
-    a.pp = op == 0 ? das_passes_per_barrier(tp, acq) : 1;
-    const size_t lds = das_gather_lds(tp, a.pp);
+    // value and d y / d c gathers share the tile plan and the LDS layout;
+    // the dynamic LDS is sized for the passes staged per barrier
+    a.pp = das_passes_per_barrier(tp, acq);
+    const size_t lds = das_gather_lds(tp, acq->n_tx, a.pp);
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
                                             groups_of(a, tp), a, lds, (hipStream_t)stream)
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
-                                                 groups_of(a, tp), a, tp.lds, (hipStream_t)stream);
+                                                 groups_of(a, tp), a, lds, (hipStream_t)stream);
     if (e == hipSuccess && a.partial)
         e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "DAS kernel launch" : "dy/dc kernel launch");
@@ -943,9 +943,11 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     // one set of 8-byte G and H windows takes the bytes of the forward's two
     // buffers of 8-byte entries; a second set, where it fits, saves a
     // barrier per pass
-    const size_t set_bytes = 2 * (size_t)wf::kChunk * tp.slot * 8;
-    const int nbuf = (WF_ADJ_TWO_SETS && tp.lds + set_bytes <= kLdsHard) ? 2 : 1;
-    const size_t lds = tp.lds + (nbuf - 1) * set_bytes;
+    const int nbuf = (WF_ADJ_TWO_SETS &&
+                      wf::das_lds(wf::das_adjoint_nbuf(2), tp.slot, acq->n_tx).total <= kLdsHard)
+                         ? 2
+                         : 1;
+    const size_t lds = wf::das_lds(wf::das_adjoint_nbuf(nbuf), tp.slot, acq->n_tx).total;
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
     for (int f = 0; f < acq->n_frames; ++f) {
         a.g = g + (size_t)f * grid->nz * grid->nx;
@@ -994,7 +996,7 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     info[3] = tp.span;
     info[4] = tp.nst;
     info[5] = tp.slot;
-    info[6] = (int32_t)das_gather_lds(tp, das_passes_per_barrier(tp, acq));
+    info[6] = (int32_t)das_gather_lds(tp, acq->n_tx, das_passes_per_barrier(tp, acq));
     info[7] = tp.ntz;
     info[8] = tp.ntx;
     info[9] = wf::kChunk;

@@ -111,9 +111,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const int slot = a.slot;
     const uint32_t buf_bytes = (uint32_t)kChunk * slot * sizeof(float2);
     float2* win = reinterpret_cast<float2*>(smem);  // 2 PP buffers of kChunk windows
-    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * PP * buf_bytes);
-    float4* q_tab = reinterpret_cast<float4*>(m_tab + a.T);
-    int* b_tab = reinterpret_cast<int*>(q_tab + a.T);
+    const DasLds lay = das_lds(das_gather_nbuf(PP), slot, a.T);
+    int4* m_tab = reinterpret_cast<int4*>(smem + lay.m_tab);
+    float4* q_tab = reinterpret_cast<float4*>(smem + lay.q_tab);
+    int* b_tab = reinterpret_cast<int*>(smem + lay.b_tab);
     // LDS byte offset of the window buffers (folded into scalar offsets)
     const uint32_t lds0 =
         (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)smem;
@@ -395,6 +396,10 @@ hipError_t allow_lds(K kernel, size_t lds) {
 
 template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG = 1, int PP = 1>
 hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
+    // the kernel carves its tables behind 2 PP window buffers: a smaller
+    // allocation would leave them outside the LDS it is given
+    if (a.pp != PP || !das_lds_fits(lds, das_gather_nbuf(PP), a.slot, a.T))
+        return hipErrorInvalidValue;
     hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
     if (e != hipSuccess) return e;
     const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
@@ -405,23 +410,23 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Batches of the large-tile shapes run 4 frames per workgroup.  16-bit RF
-// on 1024-thread tiles runs two passes per barrier (transmits of a single
-// frame, frames of a batch) where the host gave the LDS for it.  The value
-// gather only: d y / d c keeps one frame and one pass.
+// Batches of the large-tile shapes run 4 frames per workgroup (value
+// gather only: d y / d c runs one frame per workgroup).  16-bit RF on
+// 1024-thread tiles runs two passes per barrier (transmits of a single
+// frame, frames of a batch) where the host gave the LDS for it; FP32 RF
+// holds too many staging registers for two passes.
 template <int MODE, typename RT, int NT, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
+    constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
     if constexpr (OP == kOpValue) {
-        // FP32 RF holds too many staging registers for two passes
-        constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
         if (a.F > 1) {
             if constexpr (kPairs)
                 if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 4, 2>(a, lds, s);
             return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
         }
-        if constexpr (kPairs)
-            if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 1, 2>(a, lds, s);
     }
+    if constexpr (kPairs)
+        if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 1, 2>(a, lds, s);
     return launch_one<MODE, RT, NT, 2, 2, OP, 1>(a, lds, s);
 }
 

@@ -6,12 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
-namespace wf {
+#include "das_layout.h"
 
-// Channels staged per pass of the DAS kernel: their one-way receive delays
-// stay in registers while every transmit streams through LDS.
-constexpr int kChunk = 16;
-constexpr int kChunkLog2 = 4;
+namespace wf {
 // Threads per DAS workgroup (4 wave64 waves); launch plans may also use
 // 512-thread workgroups with 2 pixels per thread.
 constexpr int kThreads = 256;

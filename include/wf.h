@@ -34,13 +34,23 @@
  * Memory and streams.  Pointers documented as DEVICE are HIP device
  * pointers on the current device; HOST pointers are read during the call
  * only.  Every compute call is asynchronous on `stream` (a hipStream_t
- * passed as void*, NULL = the null stream); the library never synchronises
- * the stream.  The caller owns every buffer.  The only memory the library
- * allocates is a small per-geometry constant table (transmit and element
- * constants, a few KB) that it uploads with a blocking copy the first time
- * a geometry is seen on a device and keeps for the life of the process
- * (wf_geometry_cache_clear() frees it); do not make that first call while
- * the stream is being captured into a graph.
+ * passed as void*, NULL = the null stream).  The caller owns every buffer:
+ * RF, outputs, workspaces and the device memory of plans.
+ *
+ * Plans.  The DAS-shaped calls (wf_das_stai, wf_das_pwi, wf_das_dydc,
+ * wf_das_adjoint) need a few KB of per-geometry device tables: the
+ * per-transmit and per-channel delay constants and the work list of the
+ * launch.  With a plan (wf_plan_build_*) they live in caller-owned device
+ * memory and the call neither allocates nor synchronises: it only launches
+ * kernels on `stream`, so it may be captured into a HIP graph even for a
+ * geometry never run before.  With plan = NULL the library keeps the tables
+ * in a cache of its own: the first call of a geometry on a device
+ * allocates them (hipMalloc), writes them on `stream` and synchronises
+ * `stream`; the cache holds at most 64 geometries and evicting the least
+ * recently used one synchronises its device before freeing it.  Such calls
+ * must not be captured into graphs (a graph would keep pointers the cache
+ * may free); calls without a plan are serialised by a library lock from
+ * the table lookup to their last launch.
  *
  * Errors.  Every call validates all arguments before touching the device
  * and returns a negative wf_status with a message from wf_last_error() on
@@ -58,7 +68,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 4
+#define WF_ABI_VERSION 5
 
 typedef enum {
     WF_OK = 0,
@@ -73,6 +83,11 @@ typedef enum {
     WF_RF_F16 = 1, /* IEEE half                                           */
     WF_RF_F32 = 2  /* float                                               */
 } wf_rf_dtype;
+
+/* Opaque host handle of a plan: the launch plan of one geometry (tile
+ * shape, work split) and the location of its device tables in caller
+ * memory.  Created by wf_plan_build_*, freed by wf_plan_destroy. */
+typedef struct wf_plan wf_plan;
 
 typedef enum {
     WF_PWI_TREF_FIRST = 0, /* time zero: the first element fires          */
@@ -124,21 +139,27 @@ typedef struct {
  *              runs unsplit.  Both are deterministic; they differ only in
  *              the order of the FP32 sums.  The split depends on the
  *              geometry only, never on n_frames.
+ *   plan       NULL, or a plan built for exactly this geometry (every
+ *              field of probe, acq and grid except n_frames and dtype, and
+ *              tx_elem) on the current device; a plan built for another
+ *              geometry gives WF_ERR_INVALID_ARG.
  * Returns WF_ERR_UNSUPPORTED when the pixel spacing is so coarse that no
  * tile shape keeps a tile's delay spread inside the kernel's window.
  */
 wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
-                      const int32_t* tx_elem, const wf_grid* grid, float* out,
-                      void* workspace, uint64_t workspace_bytes, void* stream);
+                      const int32_t* tx_elem, const wf_grid* grid, const wf_plan* plan,
+                      float* out, void* workspace, uint64_t workspace_bytes, void* stream);
 
 /*
  * DAS for plane-wave imaging with coherent compounding over angles
  * (Sec. II-B).  angles_rad: HOST [n_tx] steering angles, |theta| < 80 deg.
- * tref: wf_pwi_tref.  rf, out and workspace as for wf_das_stai.
+ * tref: wf_pwi_tref.  rf, out, workspace and plan as for wf_das_stai (the
+ * plan built for these angles and tref).
  */
 wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid,
-                     float* out, void* workspace, uint64_t workspace_bytes, void* stream);
+                     const wf_plan* plan, float* out, void* workspace,
+                     uint64_t workspace_bytes, void* stream);
 
 /*
  * Bytes of the optional workspace of wf_das_stai / wf_das_pwi / wf_das_dydc
@@ -155,7 +176,9 @@ wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* ac
  *   tx_hi, tx_lo  DEVICE float [T][nz][nx]: (tau_tx - t0) * fs = hi + lo
  *   rx_hi, rx_lo  DEVICE float [C][nz][nx]: tau_rx * fs = hi + lo
  * For PWI pass angles_rad/tref, for STAI tx_elem; mode 0 = STAI, 1 = PWI.
- * acq->n_frames, n_s and dtype are ignored.
+ * acq->n_frames, n_s and dtype are ignored.  A verification call: it
+ * allocates a temporary table, writes it on `stream`, and synchronises
+ * `stream` before freeing it.
  */
 wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                     const int32_t* tx_elem, const double* angles_rad, int32_t tref,
@@ -206,12 +229,12 @@ wf_status wf_bmode(const float* bf, int32_t n_frames, int32_t nz, int32_t nx,
  * this is the derivative that lets c be learned.
  *   rf    DEVICE [F][T][C][S] as for the DAS calls.
  *   dydc  DEVICE float [F][nz][nx].
- *   workspace, workspace_bytes  as for wf_das_stai.
+ *   plan, workspace, workspace_bytes  as for wf_das_stai.
  * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
  */
 wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                      const wf_grid* grid, float* dydc, void* workspace,
+                      const wf_grid* grid, const wf_plan* plan, float* dydc, void* workspace,
                       uint64_t workspace_bytes, void* stream);
 
 /*
@@ -225,15 +248,19 @@ wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const
  *   workspace  DEVICE, 256-byte aligned, >= the bytes wf_das_adjoint_workspace
  *              reports (it holds one frame's per-tile windows; frames run one
  *              after another on `stream`); caller-owned, contents ignored.
- * Per-tile windows are accumulated with LDS float atomics and then summed in
- * a fixed tile order without global atomics: reproducible to FP32 rounding,
- * not bitwise.  Returns WF_ERR_WORKSPACE if the workspace is too small.
- * mode 0 = STAI (tx_elem), 1 = PWI (angles_rad, tref).
+ *   plan       as for wf_das_stai.
+ * Per-tile windows are accumulated in LDS as 64-bit fixed point (the
+ * cotangent rounded once per pixel to 24 bits of its frame's largest |g|)
+ * and then summed in a fixed tile order without global atomics: the
+ * result is bitwise reproducible.  Returns WF_ERR_WORKSPACE if the
+ * workspace is too small.  mode 0 = STAI (tx_elem), 1 = PWI (angles_rad,
+ * tref).
  */
 wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                          const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                         const wf_grid* grid, const float* g, float* grad_rf, void* workspace,
-                         uint64_t workspace_bytes, void* stream);
+                         const wf_grid* grid, const wf_plan* plan, const float* g,
+                         float* grad_rf, void* workspace, uint64_t workspace_bytes,
+                         void* stream);
 
 /*
  * Device bytes of the workspace wf_das_adjoint needs for this geometry (one
@@ -298,15 +325,62 @@ wf_status wf_fir(const void* rf, int32_t dtype, int64_t n_rec, int32_t n_s, cons
 wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx, int32_t wz,
                      int32_t wx, int32_t sz, int32_t sx, float* out, void* stream);
 
+/*
+ * Plans (the acquisition metadata of Sec. II-A - speed of sound, aperture,
+ * sampling frequency - with the transmit sequence and the pixel grid fix
+ * every delay table and the launch plan of the DAS calls).
+ *
+ * wf_plan_bytes_stai / wf_plan_bytes_pwi: device bytes of the plan of this
+ * geometry (host only, touches no device).  acq->n_frames and acq->dtype
+ * must be valid but do not enter the plan.
+ *
+ * wf_plan_build_stai / wf_plan_build_pwi: computes the launch plan on the
+ * host and writes the device tables into dev_mem (DEVICE, caller-owned,
+ * 256-byte aligned, >= the bytes wf_plan_bytes_* reports) with kernel
+ * launches on `stream`; returns the host handle in *out.  It sets the
+ * dynamic-LDS limit of the kernels the plan can launch on the current
+ * device (once per process) and allocates only the host handle.  The plan
+ * is valid on the current device for calls ordered after the build on
+ * `stream` (another stream must wait for it, e.g. through an event).
+ * dev_mem must stay allocated and unmodified while calls using the plan
+ * may run, graph replays included.  WF_ERR_WORKSPACE when bytes is too
+ * small; nothing is written then.
+ *
+ * wf_plan_destroy frees the host handle only (NULL is ignored); the device
+ * memory stays the caller's.  Work already enqueued with the plan keeps
+ * reading dev_mem, not the handle.
+ */
+wf_status wf_plan_bytes_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                             const wf_grid* grid, uint64_t* bytes);
+wf_status wf_plan_bytes_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
+                            int32_t tref, const wf_grid* grid, uint64_t* bytes);
+wf_status wf_plan_build_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                             const wf_grid* grid, void* dev_mem, uint64_t bytes, wf_plan** out,
+                             void* stream);
+wf_status wf_plan_build_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
+                            int32_t tref, const wf_grid* grid, void* dev_mem, uint64_t bytes,
+                            wf_plan** out, void* stream);
+void wf_plan_destroy(wf_plan* plan);
+
+/* Workspace bytes of calls made with `plan` (host only): the DAS / d y / d c
+ * split workspace for n_frames frames (0: the plan never splits; see
+ * wf_das_stai) and the adjoint workspace (one frame; see wf_das_adjoint). */
+wf_status wf_plan_workspace(const wf_plan* plan, int32_t n_frames, uint64_t* das_bytes,
+                            uint64_t* adjoint_bytes);
+
 /* Message of the last failed call on this thread ("" after success). */
 const char* wf_last_error(void);
 
 /* WF_ABI_VERSION of the loaded library. */
 int32_t wf_abi_version(void);
 
-/* Free the cached per-geometry constant tables on every device.  Must not
- * run while work that uses them is in flight. */
+/* Free the library's cache of the calls made without a plan: host plans
+ * and device tables on every device (each device is synchronised first).
+ * Plans are not affected. */
 wf_status wf_geometry_cache_clear(void);
+
+/* Geometries held by that cache and the device bytes of their tables. */
+wf_status wf_geometry_cache_info(uint64_t* entries, uint64_t* device_bytes);
 
 #ifdef __cplusplus
 }

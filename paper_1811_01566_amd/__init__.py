@@ -24,9 +24,9 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import WfError, load
 
-__all__ = ["Grid", "Scan", "das", "das_stai", "das_pwi", "delays", "envelope", "log_compress",
-           "bmode", "load", "WfError", "abi_version", "geometry_cache_clear", "tile_info",
-           "adjoint_workspace_bytes", "das_workspace_bytes",
+__all__ = ["Grid", "Scan", "Plan", "das", "das_stai", "das_pwi", "delays", "envelope",
+           "log_compress", "bmode", "load", "WfError", "abi_version", "geometry_cache_clear",
+           "geometry_cache_info", "plan_bytes", "tile_info", "adjoint_workspace_bytes", "das_workspace_bytes",
            "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd"]
 
 
@@ -74,7 +74,17 @@ def abi_version() -> int:
 
 
 def geometry_cache_clear() -> None:
+    """Free the library's cache behind calls made without a plan."""
     _lib.check(load().wf_geometry_cache_clear(), "wf_geometry_cache_clear")
+
+
+def geometry_cache_info() -> tuple:
+    """(geometries, device bytes) held by the cache behind calls made
+    without a plan."""
+    n, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _lib.check(load().wf_geometry_cache_info(ctypes.byref(n), ctypes.byref(b)),
+               "wf_geometry_cache_info")
+    return int(n.value), int(b.value)
 
 
 # ---------------------------------------------------------------------------
@@ -147,6 +157,100 @@ def _rf_dtype(t):
     return m[t.dtype]
 
 
+def _mode_args(scan: Scan, keep: _Keep):
+    mode = 0 if scan.mode == "stai" else 1
+    tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
+    ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
+    tref = _tref(scan) if mode == 1 else 0
+    return mode, tx, ang, tref
+
+
+def plan_bytes(scan: Scan, n_s: int) -> int:
+    """Device bytes of the :class:`Plan` of this scan and record length
+    (host only)."""
+    lib = load()
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, 1, n_s, _lib.WF_RF_I16)
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    n = ctypes.c_uint64(0)
+    if mode == 0:
+        st = lib.wf_plan_bytes_stai(probe, acq, tx, grid, ctypes.byref(n))
+    else:
+        st = lib.wf_plan_bytes_pwi(probe, acq, ang, tref, grid, ctypes.byref(n))
+    _lib.check(st, "wf_plan_bytes")
+    return int(n.value)
+
+
+class Plan:
+    """Launch plan and device tables of one geometry (``scan`` with records
+    of ``n_s`` samples) in caller-owned device memory, a uint8 tensor held
+    by this object.  DAS, d y / d c and adjoint calls given the plan neither
+    allocate nor synchronise, so they may be captured into HIP graphs.  The
+    tables are written on ``stream`` (default: the device's current stream);
+    calls on other streams must be ordered after it.  Keep the object alive
+    while work that uses it may run (graph replays included)."""
+
+    def __init__(self, scan: Scan, n_s: int, device=None, stream=None):
+        torch = _torch()
+        lib = load()
+        if scan.mode not in ("stai", "pwi"):
+            raise ValueError(f"mode must be 'stai' or 'pwi', got {scan.mode!r}")
+        self.scan, self.n_s, self._h = scan, int(n_s), None
+        keep = _Keep()
+        probe, acq, grid = _structs(scan, keep, 1, n_s, _lib.WF_RF_I16)
+        mode, tx, ang, tref = _mode_args(scan, keep)
+        n = ctypes.c_uint64(plan_bytes(scan, n_s))
+        dev = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.mem = torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            sp = _stream_ptr(self.mem, stream)
+            if mode == 0:
+                st = lib.wf_plan_build_stai(probe, acq, tx, grid, _dev(self.mem, "plan memory"),
+                                            n.value, ctypes.byref(h), sp)
+            else:
+                st = lib.wf_plan_build_pwi(probe, acq, ang, tref, grid,
+                                           _dev(self.mem, "plan memory"), n.value,
+                                           ctypes.byref(h), sp)
+        _lib.check(st, "wf_plan_build")
+        self._h = h
+        self.device = dev
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("the plan was closed")
+        return self._h
+
+    def workspace_bytes(self, n_frames: int = 1) -> tuple:
+        """(DAS / d y / d c split workspace for n_frames, adjoint workspace)."""
+        d, a = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _lib.check(load().wf_plan_workspace(self.handle, int(n_frames), ctypes.byref(d),
+                                            ctypes.byref(a)), "wf_plan_workspace")
+        return int(d.value), int(a.value)
+
+    def close(self):
+        """Free the host handle (the device memory goes with the tensor)."""
+        if self._h is not None and _lib._lib is not None:
+            _lib._lib.wf_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def _plan_arg(plan, scan, n_s, device):
+    if plan is None:
+        return None
+    if not isinstance(plan, Plan):
+        raise TypeError("plan must be a Plan")
+    if plan.n_s != n_s or plan.device != device:
+        raise ValueError(f"plan was built for {plan.n_s} samples on {plan.device}, "
+                         f"the call has {n_s} on {device}")
+    return plan.handle
+
+
 # ---------------------------------------------------------------------------
 # public calls
 # ---------------------------------------------------------------------------
@@ -163,12 +267,13 @@ def das_workspace_bytes(scan: Scan, n_s: int, n_frames: int = 1) -> int:
     return int(n.value)
 
 
-def _workspace_arg(scan, ns, nf, workspace, device):
+def _workspace_arg(scan, ns, nf, workspace, device, plan=None):
     """(pointer, bytes) of the DAS workspace: the caller's, or a fresh one
     when the geometry splits and none is given."""
     torch = _torch()
     if workspace is None:
-        need = das_workspace_bytes(scan, ns, nf)
+        need = plan.workspace_bytes(nf)[0] if plan is not None else das_workspace_bytes(
+            scan, ns, nf)
         if need == 0:
             return None, 0, None
         workspace = torch.empty(need, dtype=torch.uint8, device=device)
@@ -176,12 +281,13 @@ def _workspace_arg(scan, ns, nf, workspace, device):
             workspace)
 
 
-def das(scan: Scan, rf, out=None, workspace=None, stream=None):
+def das(scan: Scan, rf, out=None, workspace=None, stream=None, plan: Optional[Plan] = None):
     """Delay-and-Sum of rf [F][T][C][S] (or [T][C][S]) -> float32 [F][nz][nx]
     (or [nz][nx]).  `workspace` (uint8 device tensor of
     :func:`das_workspace_bytes`) lets grids with few tiles or uneven work
     split each tile into items run by several workgroups; it is allocated
-    when not given."""
+    when not given.  `plan` (a :class:`Plan` of this scan and record
+    length) keeps the geometry tables in caller memory."""
     torch = _torch()
     lib = load()
     squeeze = rf.dim() == 3
@@ -202,30 +308,31 @@ def das(scan: Scan, rf, out=None, workspace=None, stream=None):
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
     rfp, outp, st = _dev(rf4, "rf"), _dev(out, "out"), _stream_ptr(rf4, stream)
-    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device)
+    ph = _plan_arg(plan, scan, ns, rf.device)
+    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device, plan)
     if scan.mode == "stai":
         tx = keep.arr(ctypes.c_int32, scan.tx_elem)
-        _lib.check(lib.wf_das_stai(rfp, probe, acq, tx, grid, outp, wsp, wsb, st),
+        _lib.check(lib.wf_das_stai(rfp, probe, acq, tx, grid, ph, outp, wsp, wsb, st),
                    "wf_das_stai")
     else:
         ang = keep.arr(ctypes.c_double, scan.angles_rad)
-        _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, outp, wsp, wsb, st),
-                   "wf_das_pwi")
+        _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, ph, outp, wsp, wsb,
+                                  st), "wf_das_pwi")
     del ws_keep  # the caching allocator keeps the block until the stream is done with it
     out = out.view(nf, g.nz, g.nx)
     return out[0] if squeeze else out
 
 
-def das_stai(rf, scan: Scan, out=None, workspace=None, stream=None):
+def das_stai(rf, scan: Scan, out=None, workspace=None, stream=None, plan=None):
     if scan.mode != "stai":
         raise ValueError("scan.mode must be 'stai'")
-    return das(scan, rf, out=out, workspace=workspace, stream=stream)
+    return das(scan, rf, out=out, workspace=workspace, stream=stream, plan=plan)
 
 
-def das_pwi(rf, scan: Scan, out=None, workspace=None, stream=None):
+def das_pwi(rf, scan: Scan, out=None, workspace=None, stream=None, plan=None):
     if scan.mode != "pwi":
         raise ValueError("scan.mode must be 'pwi'")
-    return das(scan, rf, out=out, workspace=workspace, stream=stream)
+    return das(scan, rf, out=out, workspace=workspace, stream=stream, plan=plan)
 
 
 TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
@@ -360,15 +467,7 @@ def moments(env, wz: int, wx: int, sz: int, sx: int, out=None, stream=None):
     return out[0] if squeeze else out
 
 
-def _mode_args(scan: Scan, keep: _Keep):
-    mode = 0 if scan.mode == "stai" else 1
-    tx = keep.arr(ctypes.c_int32, scan.tx_elem) if mode == 0 else None
-    ang = keep.arr(ctypes.c_double, scan.angles_rad) if mode == 1 else None
-    tref = _tref(scan) if mode == 1 else 0
-    return mode, tx, ang, tref
-
-
-def das_dydc(scan: Scan, rf, out=None, workspace=None, stream=None):
+def das_dydc(scan: Scan, rf, out=None, workspace=None, stream=None, plan=None):
     """d y / d c per pixel (forward mode), rf [F][T][C][S] -> [F][nz][nx]."""
     torch = _torch()
     lib = load()
@@ -380,8 +479,9 @@ def das_dydc(scan: Scan, rf, out=None, workspace=None, stream=None):
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
     mode, tx, ang, tref = _mode_args(scan, keep)
-    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device)
-    _lib.check(lib.wf_das_dydc(mode, _dev(rf4, "rf"), probe, acq, tx, ang, tref, grid,
+    ph = _plan_arg(plan, scan, ns, rf.device)
+    wsp, wsb, ws_keep = _workspace_arg(scan, ns, nf, workspace, rf.device, plan)
+    _lib.check(lib.wf_das_dydc(mode, _dev(rf4, "rf"), probe, acq, tx, ang, tref, grid, ph,
                                _dev(out, "dydc"), wsp, wsb, _stream_ptr(rf4, stream)),
                "wf_das_dydc")
     del ws_keep
@@ -400,24 +500,27 @@ def adjoint_workspace_bytes(scan: Scan, n_s: int) -> int:
     return int(n.value)
 
 
-def das_adjoint(scan: Scan, g, n_s: int, out=None, workspace=None, stream=None):
+def das_adjoint(scan: Scan, g, n_s: int, out=None, workspace=None, stream=None, plan=None):
     """Adjoint of DAS: cotangent g [F][nz][nx] -> d L / d rf [F][T][C][S]
-    (float32; per-tile windows summed in tile order without global atomics,
-    reproducible to FP32 rounding).  `workspace` (a uint8 device tensor of at
-    least :func:`adjoint_workspace_bytes`) is allocated when not given."""
+    (float32; per-tile fixed-point windows summed in tile order without
+    global atomics, bitwise reproducible).  `workspace` (a uint8 device
+    tensor of at least :func:`adjoint_workspace_bytes`) is allocated when
+    not given."""
     torch = _torch()
     lib = load()
     g3 = g.unsqueeze(0) if g.dim() == 2 else g
     nf = g3.shape[0]
     if out is None:
         out = torch.empty((nf, scan.n_tx, scan.n_ch, n_s), dtype=torch.float32, device=g.device)
+    ph = _plan_arg(plan, scan, n_s, g.device)
     if workspace is None:
-        workspace = torch.empty(adjoint_workspace_bytes(scan, n_s), dtype=torch.uint8,
-                                device=g.device)
+        need = plan.workspace_bytes(1)[1] if plan is not None else adjoint_workspace_bytes(
+            scan, n_s)
+        workspace = torch.empty(need, dtype=torch.uint8, device=g.device)
     keep = _Keep()
     probe, acq, grid = _structs(scan, keep, nf, n_s, _lib.WF_RF_F32)
     mode, tx, ang, tref = _mode_args(scan, keep)
-    _lib.check(lib.wf_das_adjoint(mode, probe, acq, tx, ang, tref, grid, _dev(g3, "g"),
+    _lib.check(lib.wf_das_adjoint(mode, probe, acq, tx, ang, tref, grid, ph, _dev(g3, "g"),
                                   _dev(out, "grad_rf"), _dev(workspace, "workspace"),
                                   ctypes.c_uint64(workspace.numel() * workspace.element_size()),
                                   _stream_ptr(g3, stream)),
@@ -444,15 +547,19 @@ def _autograd_function():
     class DASFunction(torch.autograd.Function):
         """y = DAS(rf; c) with gradients w.r.t. the RF (adjoint kernel) and
         the speed of sound (forward-mode d y / d c reduced against dL/dy).
-        ``c`` is a 0-dim tensor; its value is read on the host."""
+        ``c`` is a 0-dim tensor; its value is read on the host.  Each
+        forward builds a :class:`Plan` for its c in torch-allocated device
+        memory, so learning c adds nothing to the library's own cache."""
 
         @staticmethod
         def forward(ctx, rf, c, scan):
             scan_c = dataclasses.replace(scan, c=float(c))
+            plan = Plan(scan_c, rf.shape[-1], device=rf.device)
             ctx.scan = scan_c
+            ctx.plan = plan
             ctx.rf_dtype = rf.dtype
             ctx.save_for_backward(rf)
-            return das(scan_c, rf)
+            return das(scan_c, rf, plan=plan)
 
         @staticmethod
         def backward(ctx, gy):
@@ -462,10 +569,11 @@ def _autograd_function():
             if ctx.needs_input_grad[0]:
                 squeeze = rf.dim() == 3
                 g3 = gy.unsqueeze(0) if squeeze else gy
-                grad_rf = das_adjoint(ctx.scan, g3, rf.shape[-1]).to(ctx.rf_dtype)
+                grad_rf = das_adjoint(ctx.scan, g3, rf.shape[-1],
+                                      plan=ctx.plan).to(ctx.rf_dtype)
                 grad_rf = grad_rf[0] if squeeze else grad_rf
             if ctx.needs_input_grad[1]:
-                dydc = das_dydc(ctx.scan, rf)
+                dydc = das_dydc(ctx.scan, rf, plan=ctx.plan)
                 grad_c = dot(gy.reshape(-1), dydc.reshape(-1)).reshape(())
             return grad_rf, grad_c, None
 

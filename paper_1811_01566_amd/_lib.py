@@ -13,7 +13,7 @@ WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
 WF_ERR_WORKSPACE = -4
-WF_ABI_VERSION = 4
+WF_ABI_VERSION = 5
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2
 WF_PWI_TREF_FIRST, WF_PWI_TREF_CENTRE = 0, 1
@@ -47,10 +47,10 @@ F = ctypes.c_float
 
 # name -> (restype, argtypes); every function declared in include/wf.h
 SIGNATURES = {
-    "wf_das_stai": (I, [V, P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), V, V, ctypes.c_uint64,
-                        V]),
-    "wf_das_pwi": (I, [V, P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), V, V, ctypes.c_uint64,
-                       V]),
+    "wf_das_stai": (I, [V, P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), V, V, V,
+                        ctypes.c_uint64, V]),
+    "wf_das_pwi": (I, [V, P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), V, V, V,
+                       ctypes.c_uint64, V]),
     "wf_das_workspace": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid),
                              ctypes.POINTER(ctypes.c_uint64)]),
     "wf_delays": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V, V, V,
@@ -58,9 +58,22 @@ SIGNATURES = {
     "wf_das_tile_info": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid),
                              c_int32_p]),
     "wf_das_dydc": (I, [I, V, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
-                        ctypes.c_uint64, V]),
+                        V, ctypes.c_uint64, V]),
     "wf_das_adjoint": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
-                           V, ctypes.c_uint64, V]),
+                           V, V, ctypes.c_uint64, V]),
+    "wf_plan_bytes_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid),
+                               ctypes.POINTER(ctypes.c_uint64)]),
+    "wf_plan_bytes_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid),
+                              ctypes.POINTER(ctypes.c_uint64)]),
+    "wf_plan_build_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), V, ctypes.c_uint64,
+                               ctypes.POINTER(V), V]),
+    "wf_plan_build_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), V,
+                              ctypes.c_uint64, ctypes.POINTER(V), V]),
+    "wf_plan_destroy": (None, [V]),
+    "wf_plan_workspace": (I, [V, I, ctypes.POINTER(ctypes.c_uint64),
+                              ctypes.POINTER(ctypes.c_uint64)]),
+    "wf_geometry_cache_info": (I, [ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
     "wf_das_adjoint_workspace": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I,
                                      P(WfGrid), ctypes.POINTER(ctypes.c_uint64)]),
     "wf_dot": (I, [V, V, ctypes.c_int64, V, V]),

@@ -1,10 +1,22 @@
 """Compile libwf.so (HIP for gfx950) in-tree.
 
-    python -m paper_1811_01566_amd.build
+    python -m paper_1811_01566_amd.build             # libwf.so
+    python -m paper_1811_01566_amd.build --sanitize  # libwf_asan.so
 
 Packed FP32 instructions are disabled for device code
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``); the host pass warns
 that it does not know the feature, which is harmless.
+
+``--sanitize`` builds the host library (argument checks, launch and split
+planning, plans and the geometry cache in ``api.cpp``) with the host
+compiler under AddressSanitizer and UndefinedBehaviorSanitizer, and links it
+with the kernels built as usual (no sanitizer in device code).  Load it
+through ``WF_LIB`` with the sanitizer runtimes preloaded, e.g.
+
+    LD_PRELOAD="$(g++ -print-file-name=libasan.so) $(g++ -print-file-name=libubsan.so)" \
+    ASAN_OPTIONS=detect_leaks=0 UBSAN_OPTIONS=halt_on_error=1:print_stacktrace=1 \
+    WF_LIB=paper_1811_01566_amd/libwf_asan.so python -m pytest tests -m "not gpu" -k \
+        "abi or tile_plan or plan_cpu or das_layout"
 """
 
 from __future__ import annotations
@@ -52,5 +64,58 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     return out
 
 
+LIB_ASAN = os.path.join(HERE, "libwf_asan.so")
+HOST_SOURCES = ["api.cpp"]
+
+
+def build_sanitized(verbose: bool = False, out: str = LIB_ASAN) -> str:
+    """libwf with the host code under ASan + UBSan (see the module doc)."""
+    import tempfile
+
+    cxx = os.environ.get("CXX") or shutil.which("g++")
+    if not cxx:
+        raise RuntimeError("no host C++ compiler for the sanitized build")
+    san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    inc = f"-I{os.path.join(ROOT, 'include')}"
+    with tempfile.TemporaryDirectory() as tmp:
+        objs, cmds = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmp, src + ".o")
+            objs.append(obj)
+            if src in HOST_SOURCES:
+                cmds.append([cxx, "-std=c++17", "-O1", "-g", "-fPIC", "-Wall", *san,
+                             "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", inc, "-c",
+                             os.path.join(CSRC, src), "-o", obj])
+            else:
+                cmds.append([hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+                             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                             "-Wno-unused-command-line-argument", inc, "-c",
+                             os.path.join(CSRC, src), "-o", obj])
+        procs = []
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                          text=True))
+        for p in procs:
+            log = p.communicate()[0]
+            if p.returncode != 0:
+                sys.stderr.write(log)
+                raise RuntimeError(f"compile failed: {' '.join(p.args)}")
+        link = [cxx, "-shared", *san, "-o", out + ".tmp", *objs, "-L/opt/rocm/lib",
+                "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+        if verbose:
+            print(" ".join(link), flush=True)
+        r = subprocess.run(link, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("link failed")
+        os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if "--sanitize" in sys.argv[1:]:
+        print(build_sanitized(verbose=True))
+    else:
+        print(build(verbose=True))

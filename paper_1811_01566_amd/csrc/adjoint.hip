@@ -323,16 +323,14 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(const float* a, const 
 
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
-    if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), lds);
 }
 
 template <int MODE, int NT, int PX, int NB>
 hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
     if (!das_lds_fits(lds, das_adjoint_nbuf(NB), a.slot, a.T)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(das_adjoint_kernel<MODE, NT, PX, NB>, lds);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || a.prepare_only) return e;
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, (unsigned)a.F, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), (unsigned)a.F, (unsigned)a.nsplit);
     hipLaunchKernelGGL((das_adjoint_kernel<MODE, NT, PX, NB>), grid, dim3(NT), lds, s, a);

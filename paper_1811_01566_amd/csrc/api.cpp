@@ -8,10 +8,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <map>
+#include <list>
+#include <memory>
 #include <mutex>
 #include <queue>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/wf.h"
@@ -217,55 +219,7 @@ void build_geometry(int mode, const wf_probe* probe, const wf_acq* acq, const in
     }
 }
 
-struct CacheEntry {
-    void* dev = nullptr;
-    const wf::TxConst* tx = nullptr;
-    const wf::ChConst* ch = nullptr;
-};
-
-std::mutex g_mu;
-std::map<std::string, CacheEntry> g_cache;
-
 void key_add(std::string& k, const void* p, size_t n) { k.append((const char*)p, n); }
-
-wf_status device_tables(int mode, const wf_probe* probe, const wf_acq* acq,
-                        const int32_t* tx_elem, const double* angles, int32_t tref,
-                        const wf_grid* grid, Geometry* g, CacheEntry* out) {
-    build_geometry(mode, probe, acq, tx_elem, angles, tref, grid, g);
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::string key;
-    key_add(key, &dev, sizeof dev);
-    key_add(key, &mode, sizeof mode);
-    key_add(key, g->tx.data(), g->tx.size() * sizeof(wf::TxConst));
-    key_add(key, g->ch.data(), g->ch.size() * sizeof(wf::ChConst));
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-        *out = it->second;
-        return WF_OK;
-    }
-    const size_t txb = g->tx.size() * sizeof(wf::TxConst);
-    const size_t chb = g->ch.size() * sizeof(wf::ChConst);
-    void* mem = nullptr;
-    e = hipMalloc(&mem, txb + chb);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(geometry table)");
-    e = hipMemcpy(mem, g->tx.data(), txb, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy((char*)mem + txb, g->ch.data(), chb, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(mem);
-        return hip_fail(e, "hipMemcpy(geometry table)");
-    }
-    CacheEntry ce;
-    ce.dev = mem;
-    ce.tx = (const wf::TxConst*)mem;
-    ce.ch = (const wf::ChConst*)((char*)mem + txb);
-    g_cache.emplace(key, ce);
-    *out = ce;
-    return WF_OK;
-}
 
 // ---------------------------------------------------------------------------
 // DAS tile selection
@@ -354,79 +308,15 @@ bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, Tile
     return false;
 }
 
-// Passes the value gather stages per barrier: two (four window buffers)
-// for 16-bit RF on 1024-thread tiles, where one workgroup fills a CU and
-// the buffers fit the LDS; FP32 staging would spill registers.
 // LDS bytes of a gather workgroup staging pp passes per barrier.
 size_t das_gather_lds(const TilePlan& tp, int T, int pp) {
     return wf::das_lds(wf::das_gather_nbuf(pp), tp.slot, T).total;
-}
-
-int das_passes_per_barrier(const TilePlan& tp, const wf_acq* acq) {
-    return WF_DAS_TWO_PASS && tp.threads == 1024 && acq->dtype != WF_RF_F32 &&
-                   das_gather_lds(tp, acq->n_tx, 2) <= kLdsHard
-               ? 2
-               : 1;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const char* pa = (const char*)a;
     const char* pb = (const char*)b;
     return pa < pb + nb && pb < pa + na;
-}
-
-// Validates a DAS-shaped call and fills the kernel arguments and plan.
-wf_status prepare_das(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
-                      const double* angles, int32_t tref, const wf_grid* grid, wf::DasArgs* a,
-                      TilePlan* tp, Geometry* gout = nullptr) {
-    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
-    if (st != WF_OK) return st;
-    Geometry g;
-    CacheEntry ce;
-    st = device_tables(mode, probe, acq, tx_elem, angles, tref, grid, &g, &ce);
-    if (st != WF_OK) return st;
-    if (!choose_tile(g, acq, grid, tp))
-        return fail(WF_ERR_UNSUPPORTED,
-                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
-                    g.dzs, g.dxs);
-    if ((long long)tp->ntz * tp->ntx > 0x7FFFFFFF)
-        return fail(WF_ERR_UNSUPPORTED, "too many tiles");
-    *a = wf::DasArgs{};
-    a->F = acq->n_frames;
-    a->T = acq->n_tx;
-    a->C = acq->n_ch;
-    a->S = acq->n_s;
-    a->nz = grid->nz;
-    a->nx = grid->nx;
-    a->tz_log2 = tp->tz_log2;
-    a->ntz = tp->ntz;
-    a->ntx = tp->ntx;
-    a->xcd_order = (WF_DAS_XCD_ORDER && (tp->ntz * tp->ntx) % 8 == 0) ? 1 : 0;
-    a->nsplit = 1;  // no channel split unless the caller's workspace allows one
-    a->split_chunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
-    a->nts = 1;
-    a->split_tx = acq->n_tx;
-    a->partial = nullptr;
-    a->ng = tp->nst / 8;
-    a->nst = tp->nst;
-    a->slot = tp->slot;
-    a->txspan_q = (uint32_t)tp->span << wf::kQBits;
-    a->rxspan_q = (uint32_t)tp->span << wf::kQBits;
-    a->Z0 = g.Z0;
-    a->dZ = g.dZ;
-    a->dX = g.dX;
-    a->O = g.O;
-    a->fnum2 = g.fnum2;
-    a->dxq = g.dxq;
-    a->inv_dxq = 1.0f / g.dxq;
-    a->x0f = g.x0f;
-    a->dxf = g.dxf;
-    a->t0fs = (float)(acq->t0 * acq->fs);
-    a->neg_inv_c = (float)(-1.0 / acq->c);
-    a->tx_tab = ce.tx;
-    a->ch_tab = ce.ch;
-    if (gout) *gout = std::move(g);
-    return WF_OK;
 }
 
 size_t rf_bytes_of(const wf_acq* acq) {
@@ -463,7 +353,6 @@ struct SplitPlan {
     // work list: the items that run any pass (code tile * nsplit + split),
     // heaviest first; empty for grids left to the plain grid order
     std::vector<int> order;
-    std::string key;  // geometry key of the plan (device copies of `order`)
 };
 
 // Transmit passes the gather runs for each (tile, channel chunk, transmit),
@@ -601,9 +490,6 @@ double plan_time(const SplitPlan& sp, const std::vector<double>& cost,
     return end + extra / pass_s;
 }
 
-std::mutex g_split_mu;
-std::map<std::string, SplitPlan> g_split_cache;
-
 // The split of a geometry: the candidate (chunks per split x transmit
 // splits of 1, 2 or 4) with the least plan_time.  It depends on the
 // geometry and the tile plan only, never on the frame count, so a batch and
@@ -624,21 +510,6 @@ SplitPlan plan_split(int mode, const Geometry& g, const wf_acq* acq, const wf_gr
     // the pass map holds tiles x chunks x (T + 1) counts: planning is skipped
     // beyond 32 M of them (64 MB), where the tiles outnumber the slots anyway
     if (tiles * nch * (T + 1LL) > (32LL << 20)) return base;
-
-    std::string key;
-    key_add(key, &mode, sizeof mode);
-    const int dims[] = {acq->n_tx, acq->n_ch, acq->n_s, grid->nz, grid->nx, tp.threads, tp.px,
-                        tp.tz_log2, tp.nst, (int)tp.lds};
-    key_add(key, dims, sizeof dims);
-    const float geo[] = {g.Z0.x, g.dZ.x, g.x0f, g.dxf, g.fnum2, g.O.x};
-    key_add(key, geo, sizeof geo);
-    key_add(key, g.tx.data(), g.tx.size() * sizeof(wf::TxConst));
-    key_add(key, g.ch.data(), g.ch.size() * sizeof(wf::ChConst));
-    {
-        std::lock_guard<std::mutex> lk(g_split_mu);
-        auto it = g_split_cache.find(key);
-        if (it != g_split_cache.end()) return it->second;
-    }
 
     std::vector<uint16_t> pre;
     pass_map(mode, g, acq, grid, tp, &pre);
@@ -689,52 +560,398 @@ SplitPlan plan_split(int mode, const Geometry& g, const wf_acq* acq, const wf_gr
                 best = c.first;
             }
     }
-    best.key = key;
-    std::lock_guard<std::mutex> lk(g_split_mu);
-    g_split_cache.emplace(key, best);
     return best;
 }
 
-// Device copy of a plan's work list on the current device (cached with
-// the geometry tables; freed by wf_geometry_cache_clear).
-std::map<std::string, int*> g_items_cache;
+size_t split_ws_bytes(const SplitPlan& sp, int n_frames, int nz, int nx) {
+    return sp.nsplit > 1 ? (size_t)sp.nsplit * n_frames * nz * nx * 4 : 0;
+}
 
-wf_status device_items(const SplitPlan& sp, const int** out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::string key = sp.key;
-    key_add(key, &dev, sizeof dev);
-    const int shape[] = {sp.nsplit, sp.chunks, sp.nts, sp.txs};
-    key_add(key, shape, sizeof shape);
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_items_cache.find(key);
-    if (it != g_items_cache.end()) {
-        *out = it->second;
-        return WF_OK;
-    }
-    int* mem = nullptr;
-    const size_t bytes = sp.order.size() * sizeof(int);
-    e = hipMalloc(&mem, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
-    e = hipMemcpy(mem, sp.order.data(), bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(mem);
-        return hip_fail(e, "hipMemcpy(work list)");
-    }
-    g_items_cache.emplace(key, mem);
-    *out = mem;
+// ---------------------------------------------------------------------------
+// plans: host half (geometry, tile plan, work split) and device tables
+// ---------------------------------------------------------------------------
+
+// Everything a DAS-shaped launch needs on the host for one geometry.  Two
+// calls with equal keys run the same tiles, windows, delays and items.
+struct PlanCore {
+    int mode = 0;
+    int n_tx = 0, n_ch = 0, n_s = 0, nz = 0, nx = 0;
+    Geometry g;
+    TilePlan tp;
+    SplitPlan sp;
+    std::string key;
+};
+
+// The key of a geometry: the dimensions and every float the kernels or the
+// planner read, including the per-transmit and per-channel tables (which
+// carry the speed of sound, sampling rate, time origin, probe and grid).
+std::string geometry_key(int mode, const wf_acq* acq, const wf_grid* grid, const Geometry& g) {
+    std::string k;
+    const int32_t dims[] = {mode, acq->n_tx, acq->n_ch, acq->n_s, grid->nz, grid->nx};
+    key_add(k, dims, sizeof dims);
+    const float f[] = {g.Z0.x, g.Z0.y, g.dZ.x, g.dZ.y, g.dX.x, g.dX.y, g.O.x,
+                       g.O.y,  g.x0f,  g.dxf,  g.fnum2, g.dxq};
+    key_add(k, f, sizeof f);
+    const double d[] = {g.dzs, g.dxs};
+    key_add(k, d, sizeof d);
+    key_add(k, g.tx.data(), g.tx.size() * sizeof(wf::TxConst));
+    key_add(k, g.ch.data(), g.ch.size() * sizeof(wf::ChConst));
+    return k;
+}
+
+// Tile plan and work split of a geometry whose `g` and `key` are filled.
+// The split comes from a dispatch simulation over the pass map: up to a few
+// milliseconds of host time on the largest grids.
+wf_status plan_core(const wf_acq* acq, const wf_grid* grid, PlanCore* c) {
+    if (!choose_tile(c->g, acq, grid, &c->tp))
+        return fail(WF_ERR_UNSUPPORTED,
+                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
+                    c->g.dzs, c->g.dxs);
+    if ((long long)c->tp.ntz * c->tp.ntx > 0x7FFFFFFF)
+        return fail(WF_ERR_UNSUPPORTED, "too many tiles");
+    c->sp = plan_split(c->mode, c->g, acq, grid, c->tp);
     return WF_OK;
 }
 
-size_t split_ws_bytes(const SplitPlan& sp, const wf_acq* acq, const wf_grid* grid) {
-    return sp.nsplit > 1 ? (size_t)sp.nsplit * acq->n_frames * grid->nz * grid->nx * 4 : 0;
+// Geometry and key of a validated call (cheap: O(elements + transmits +
+// channels)); plan_core adds the tile plan and split.
+void begin_core(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                const double* angles, int32_t tref, const wf_grid* grid, PlanCore* c) {
+    c->mode = mode;
+    c->n_tx = acq->n_tx;
+    c->n_ch = acq->n_ch;
+    c->n_s = acq->n_s;
+    c->nz = grid->nz;
+    c->nx = grid->nx;
+    build_geometry(mode, probe, acq, tx_elem, angles, tref, grid, &c->g);
+    c->key = geometry_key(mode, acq, grid, c->g);
+}
+
+wf_status make_core(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                    const double* angles, int32_t tref, const wf_grid* grid, PlanCore* c) {
+    begin_core(mode, probe, acq, tx_elem, angles, tref, grid, c);
+    return plan_core(acq, grid, c);
+}
+
+// Device tables of a plan, inside one block of device memory:
+// [TxConst x T][ChConst x C][int x work-list items], each part 256-byte
+// aligned.
+struct DevTables {
+    const wf::TxConst* tx = nullptr;
+    const wf::ChConst* ch = nullptr;
+    const int* items = nullptr;  // null when the plan has no work list
+};
+
+constexpr size_t kTableAlign = 256;
+size_t align_up(size_t v) { return (v + kTableAlign - 1) & ~(kTableAlign - 1); }
+
+struct TableLayout {
+    size_t ch, items, total;
+};
+
+TableLayout table_layout(const PlanCore& c) {
+    TableLayout L;
+    L.ch = align_up(c.g.tx.size() * sizeof(wf::TxConst));
+    L.items = align_up(L.ch + c.g.ch.size() * sizeof(wf::ChConst));
+    L.total = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
+    return L;
+}
+
+// Writes the tables into `mem` (at least table_layout().total bytes) with
+// kernel launches on `s`: stream-ordered, and capturable.
+wf_status upload_tables(const PlanCore& c, void* mem, hipStream_t s, DevTables* out) {
+    const TableLayout L = table_layout(c);
+    char* m = static_cast<char*>(mem);
+    hipError_t e = wf::launch_store(m, c.g.tx.data(), c.g.tx.size() * sizeof(wf::TxConst), s);
+    if (e == hipSuccess)
+        e = wf::launch_store(m + L.ch, c.g.ch.data(), c.g.ch.size() * sizeof(wf::ChConst), s);
+    if (e == hipSuccess && !c.sp.order.empty())
+        e = wf::launch_store(m + L.items, c.sp.order.data(), c.sp.order.size() * sizeof(int), s);
+    if (e != hipSuccess) return hip_fail(e, "plan table upload");
+    out->tx = reinterpret_cast<const wf::TxConst*>(m);
+    out->ch = reinterpret_cast<const wf::ChConst*>(m + L.ch);
+    out->items = c.sp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.items);
+    return WF_OK;
+}
+
+// Passes the value and d y / d c gathers stage per barrier: two (four
+// window buffers) for 16-bit RF on 1024-thread tiles, where one workgroup
+// fills a CU and the buffers fit the LDS; FP32 staging would spill.
+int das_passes_per_barrier(const TilePlan& tp, int T, int dtype) {
+    return WF_DAS_TWO_PASS && tp.threads == 1024 && dtype != WF_RF_F32 &&
+                   das_gather_lds(tp, T, 2) <= kLdsHard
+               ? 2
+               : 1;
+}
+
+// Window sets of the adjoint: two where they fit the LDS (a pass then
+// needs one barrier instead of two).
+int adjoint_sets(const TilePlan& tp, int T) {
+    return WF_ADJ_TWO_SETS &&
+                   wf::das_lds(wf::das_adjoint_nbuf(2), tp.slot, T).total <= kLdsHard
+               ? 2
+               : 1;
+}
+
+void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
+               wf::DasArgs* a);
+
+// Sets the dynamic-LDS limit of every kernel a plan can launch (each RF
+// type, single frames and batches, value and d y / d c gathers, the
+// adjoint), so calls with the plan, graph capture included, make no
+// attribute call.
+wf_status prepare_kernels(const PlanCore& c, const wf_acq* acq, const wf_grid* grid) {
+    const TilePlan& tp = c.tp;
+    const int T = acq->n_tx;
+    wf::DasArgs a;
+    fill_args(c, DevTables{}, acq, grid, &a);
+    a.prepare_only = 1;
+    const int groups = (wf::kChunk * a.ng + tp.threads - 1) / tp.threads;
+    for (int dtype = WF_RF_I16; dtype <= WF_RF_F32; ++dtype)
+        for (int F : {1, 2}) {
+            a.F = F;
+            a.pp = das_passes_per_barrier(tp, T, dtype);
+            const size_t lds = das_gather_lds(tp, T, a.pp);
+            hipError_t e = wf::launch_das(c.mode, dtype, tp.threads, tp.px, groups, a, lds, 0);
+            if (e == hipSuccess)
+                e = wf::launch_das_dydc(c.mode, dtype, tp.threads, tp.px, groups, a, lds, 0);
+            if (e != hipSuccess) return hip_fail(e, "DAS kernel attributes");
+        }
+    a.F = 1;
+    const int nbuf = adjoint_sets(tp, T);
+    hipError_t e = wf::launch_das_adjoint(
+        c.mode, tp.threads, tp.px, nbuf, a,
+        wf::das_lds(wf::das_adjoint_nbuf(nbuf), tp.slot, T).total, 0);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel attributes");
+    return WF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the cache behind calls made without a plan: bounded, least recently used
+// ---------------------------------------------------------------------------
+
+#ifndef WF_GEOMETRY_CACHE_ENTRIES
+#define WF_GEOMETRY_CACHE_ENTRIES 64
+#endif
+
+struct Upload {
+    int device = 0;
+    void* mem = nullptr;
+    size_t bytes = 0;
+    DevTables t;
+};
+
+struct CacheEntry {
+    std::shared_ptr<const PlanCore> core;
+    std::vector<Upload> uploads;  // device tables, per device that used them
+};
+
+// Entries hold host plans (for the size and plan queries) and, once a call
+// ran on a device, library-owned device tables.  The mutex is held from the
+// lookup through the launches of a call made without a plan, so an entry
+// is never evicted between its lookup and the launches that read it;
+// eviction synchronises the device before it frees the tables.
+struct GeometryCache {
+    std::mutex mu;
+    std::list<std::pair<std::string, CacheEntry>> lru;  // most recent first
+    std::unordered_map<std::string, std::list<std::pair<std::string, CacheEntry>>::iterator>
+        index;
+    size_t device_bytes = 0;
+};
+
+GeometryCache& cache() {
+    static GeometryCache* c = new GeometryCache;  // never destroyed: no teardown order issue
+    return *c;
+}
+
+hipError_t free_uploads(CacheEntry& e) {
+    hipError_t first = hipSuccess;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (Upload& u : e.uploads) {
+        hipError_t r = hipSetDevice(u.device);
+        if (r == hipSuccess) r = hipDeviceSynchronize();  // work in flight may read it
+        if (r == hipSuccess) r = hipFree(u.mem);
+        if (r != hipSuccess && first == hipSuccess) first = r;
+        cache().device_bytes -= u.bytes;
+    }
+    e.uploads.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+    return first;
+}
+
+// Host plan of a geometry through the cache (lock held by the caller).
+wf_status cached_core(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                      const double* angles, int32_t tref, const wf_grid* grid,
+                      CacheEntry** out) {
+    GeometryCache& gc = cache();
+    PlanCore c;
+    begin_core(mode, probe, acq, tx_elem, angles, tref, grid, &c);
+    auto it = gc.index.find(c.key);
+    if (it != gc.index.end()) {
+        gc.lru.splice(gc.lru.begin(), gc.lru, it->second);
+        *out = &it->second->second;
+        return WF_OK;
+    }
+    wf_status st = plan_core(acq, grid, &c);
+    if (st != WF_OK) return st;
+    while (gc.lru.size() >= WF_GEOMETRY_CACHE_ENTRIES) {
+        auto& victim = gc.lru.back();
+        hipError_t e = free_uploads(victim.second);
+        gc.index.erase(victim.first);
+        gc.lru.pop_back();
+        if (e != hipSuccess) return hip_fail(e, "freeing an evicted geometry table");
+    }
+    std::string key = c.key;
+    CacheEntry ce;
+    ce.core = std::make_shared<const PlanCore>(std::move(c));
+    gc.lru.emplace_front(key, std::move(ce));
+    gc.index[key] = gc.lru.begin();
+    *out = &gc.lru.front().second;
+    return WF_OK;
+}
+
+// Device tables of a cached entry on the current device: allocated and
+// uploaded on first use, then `s` is synchronised so that calls on other
+// streams may read them (lock held by the caller).
+wf_status cached_tables(CacheEntry& ce, hipStream_t s, DevTables* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    for (const Upload& u : ce.uploads)
+        if (u.device == dev) {
+            *out = u.t;
+            return WF_OK;
+        }
+    Upload u;
+    u.device = dev;
+    u.bytes = table_layout(*ce.core).total;
+    e = hipMalloc(&u.mem, u.bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(geometry table)");
+    wf_status st = upload_tables(*ce.core, u.mem, s, &u.t);
+    if (st == WF_OK) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "geometry table upload");
+    }
+    if (st != WF_OK) {
+        (void)hipFree(u.mem);
+        return st;
+    }
+    cache().device_bytes += u.bytes;
+    ce.uploads.push_back(u);
+    *out = u.t;
+    return WF_OK;
+}
+
+}  // namespace
+
+// The caller-facing plan: a host plan and the device tables it wrote into
+// caller-owned memory on one device.
+struct wf_plan {
+    uint64_t magic;
+    std::shared_ptr<const PlanCore> core;
+    int device;
+    DevTables t;
+};
+
+namespace {
+
+constexpr uint64_t kPlanMagic = 0x316e616c705f6677ULL;  // "wf_plan1"
+
+// The plan a DAS-shaped call runs with: the caller's, checked against the
+// call's geometry, or the cache's.  Without a plan `lk` takes the cache
+// lock and keeps it until the caller's launches are issued.
+struct Resolved {
+    std::shared_ptr<const PlanCore> core;
+    DevTables t;
+};
+
+wf_status resolve(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                  const double* angles, int32_t tref, const wf_grid* grid, const wf_plan* plan,
+                  hipStream_t s, std::unique_lock<std::mutex>* lk, Resolved* r) {
+    if (plan) {
+        if (plan->magic != kPlanMagic) return fail(WF_ERR_INVALID_ARG, "plan is not a live wf_plan");
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (dev != plan->device)
+            return fail(WF_ERR_INVALID_ARG, "plan was built on device %d, the call runs on %d",
+                        plan->device, dev);
+        Geometry g;
+        build_geometry(mode, probe, acq, tx_elem, angles, tref, grid, &g);
+        if (plan->core->mode != mode || geometry_key(mode, acq, grid, g) != plan->core->key)
+            return fail(WF_ERR_INVALID_ARG,
+                        "plan was built for another geometry (mode, sizes, probe, transmits, "
+                        "channels, speed of sound, sampling or grid differ)");
+        r->core = plan->core;
+        r->t = plan->t;
+        return WF_OK;
+    }
+    *lk = std::unique_lock<std::mutex>(cache().mu);
+    CacheEntry* ce = nullptr;
+    wf_status st = cached_core(mode, probe, acq, tx_elem, angles, tref, grid, &ce);
+    if (st != WF_OK) return st;
+    if ((st = cached_tables(*ce, s, &r->t)) != WF_OK) return st;
+    r->core = ce->core;
+    return WF_OK;
+}
+
+// Host plan for the size and plan queries (through the cache; no device).
+wf_status query_core(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                     const double* angles, int32_t tref, const wf_grid* grid,
+                     std::shared_ptr<const PlanCore>* out) {
+    std::lock_guard<std::mutex> lk(cache().mu);
+    CacheEntry* ce = nullptr;
+    wf_status st = cached_core(mode, probe, acq, tx_elem, angles, tref, grid, &ce);
+    if (st == WF_OK) *out = ce->core;
+    return st;
+}
+
+// Kernel arguments of a plan (frames, RF, outputs and split set by callers).
+void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
+               wf::DasArgs* a) {
+    const Geometry& g = c.g;
+    const TilePlan& tp = c.tp;
+    *a = wf::DasArgs{};
+    a->F = acq->n_frames;
+    a->T = acq->n_tx;
+    a->C = acq->n_ch;
+    a->S = acq->n_s;
+    a->nz = grid->nz;
+    a->nx = grid->nx;
+    a->tz_log2 = tp.tz_log2;
+    a->ntz = tp.ntz;
+    a->ntx = tp.ntx;
+    a->xcd_order = (WF_DAS_XCD_ORDER && (tp.ntz * tp.ntx) % 8 == 0) ? 1 : 0;
+    a->nsplit = 1;  // no split unless the caller's workspace allows one
+    a->split_chunks = (acq->n_ch + wf::kChunk - 1) / wf::kChunk;
+    a->nts = 1;
+    a->split_tx = acq->n_tx;
+    a->partial = nullptr;
+    a->ng = tp.nst / 8;
+    a->nst = tp.nst;
+    a->slot = tp.slot;
+    a->txspan_q = (uint32_t)tp.span << wf::kQBits;
+    a->rxspan_q = (uint32_t)tp.span << wf::kQBits;
+    a->Z0 = g.Z0;
+    a->dZ = g.dZ;
+    a->dX = g.dX;
+    a->O = g.O;
+    a->fnum2 = g.fnum2;
+    a->dxq = g.dxq;
+    a->inv_dxq = 1.0f / g.dxq;
+    a->x0f = g.x0f;
+    a->dxf = g.dxf;
+    a->t0fs = (float)(acq->t0 * acq->fs);
+    a->neg_inv_c = (float)(-1.0 / acq->c);
+    a->tx_tab = t.tx;
+    a->ch_tab = t.ch;
 }
 
 wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const int32_t* tx_elem, const double* angles, int32_t tref,
-                     const wf_grid* grid, float* out, void* workspace, uint64_t ws_bytes,
-                     void* stream) {
+                     const wf_grid* grid, const wf_plan* plan, float* out, void* workspace,
+                     uint64_t ws_bytes, void* stream) {
     wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
     if ((st = check_rf(rf, acq)) != WF_OK) return st;
@@ -743,15 +960,18 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
     const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
     if (overlaps(rf, rf_bytes_of(acq), out, out_bytes))
         return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
-    wf::DasArgs a;
-    TilePlan tp;
-    Geometry g;
-    if ((st = prepare_das(mode, probe, acq, tx_elem, angles, tref, grid, &a, &tp, &g)) != WF_OK)
+    std::unique_lock<std::mutex> lk;
+    Resolved r;
+    if ((st = resolve(mode, probe, acq, tx_elem, angles, tref, grid, plan, (hipStream_t)stream,
+                      &lk, &r)) != WF_OK)
         return st;
+    const TilePlan& tp = r.core->tp;
+    const SplitPlan& sp = r.core->sp;
+    wf::DasArgs a;
+    fill_args(*r.core, r.t, acq, grid, &a);
     a.rf = rf;
     a.out = out;
-    const SplitPlan sp = plan_split(mode, g, acq, grid, tp);
-    const size_t need = split_ws_bytes(sp, acq, grid);
+    const size_t need = split_ws_bytes(sp, acq->n_frames, grid->nz, grid->nx);
     const bool split = need > 0 && workspace && ws_bytes >= need;
     if (split) {
         if (((uintptr_t)workspace & 3) != 0)
@@ -774,7 +994,7 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
                               : sp.nsplit == 1 && !sp.order.empty() &&
                                     (long long)sp.order.size() < all_items;
     if (listed) {
-        if ((st = device_items(sp, &a.items)) != WF_OK) return st;
+        a.items = r.t.items;
         a.nitems = (int)sp.order.size();
         if ((long long)sp.order.size() < all_items) {
             float* clear = split ? a.partial : out;
@@ -785,7 +1005,7 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
     }
     // value and d y / d c gathers share the tile plan and the LDS layout;
     // the dynamic LDS is sized for the passes staged per barrier
-    a.pp = das_passes_per_barrier(tp, acq);
+    a.pp = das_passes_per_barrier(tp, acq->n_tx, acq->dtype);
     const size_t lds = das_gather_lds(tp, acq->n_tx, a.pp);
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
                                             groups_of(a, tp), a, lds, (hipStream_t)stream)
@@ -817,26 +1037,27 @@ int32_t wf_abi_version(void) { return WF_ABI_VERSION; }
 const char* wf_last_error(void) { return g_err.c_str(); }
 
 wf_status wf_das_stai(const void* rf, const wf_probe* probe, const wf_acq* acq,
-                      const int32_t* tx_elem, const wf_grid* grid, float* out, void* workspace,
-                      uint64_t workspace_bytes, void* stream) {
-    return das_common(0, 0, rf, probe, acq, tx_elem, nullptr, 0, grid, out, workspace,
+                      const int32_t* tx_elem, const wf_grid* grid, const wf_plan* plan,
+                      float* out, void* workspace, uint64_t workspace_bytes, void* stream) {
+    return das_common(0, 0, rf, probe, acq, tx_elem, nullptr, 0, grid, plan, out, workspace,
                       workspace_bytes, stream);
 }
 
 wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
-                     const double* angles_rad, int32_t tref, const wf_grid* grid, float* out,
-                     void* workspace, uint64_t workspace_bytes, void* stream) {
-    return das_common(1, 0, rf, probe, acq, nullptr, angles_rad, tref, grid, out, workspace,
-                      workspace_bytes, stream);
+                     const double* angles_rad, int32_t tref, const wf_grid* grid,
+                     const wf_plan* plan, float* out, void* workspace, uint64_t workspace_bytes,
+                     void* stream) {
+    return das_common(1, 0, rf, probe, acq, nullptr, angles_rad, tref, grid, plan, out,
+                      workspace, workspace_bytes, stream);
 }
 
 wf_status wf_das_dydc(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
                       const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                      const wf_grid* grid, float* dydc, void* workspace,
+                      const wf_grid* grid, const wf_plan* plan, float* dydc, void* workspace,
                       uint64_t workspace_bytes, void* stream) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
     return das_common(mode, 1, rf, probe, acq, mode == 0 ? tx_elem : nullptr,
-                      mode == 1 ? angles_rad : nullptr, tref, grid, dydc, workspace,
+                      mode == 1 ? angles_rad : nullptr, tref, grid, plan, dydc, workspace,
                       workspace_bytes, stream);
 }
 
@@ -845,23 +1066,21 @@ wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* ac
                            const wf_grid* grid, uint64_t* bytes) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
     if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
-    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    const int32_t* tx = mode == 0 ? tx_elem : nullptr;
+    const double* ang = mode == 1 ? angles_rad : nullptr;
+    wf_status st = check_geometry(mode, probe, acq, tx, ang, tref, grid, true);
     if (st != WF_OK) return st;
-    Geometry g;
-    build_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                   mode == 1 ? angles_rad : nullptr, tref, grid, &g);
-    TilePlan tp;
-    if (!choose_tile(g, acq, grid, &tp))
-        return fail(WF_ERR_UNSUPPORTED, "pixel spacing too coarse for the DAS tile window");
-    *bytes = split_ws_bytes(plan_split(mode, g, acq, grid, tp), acq, grid);
+    std::shared_ptr<const PlanCore> c;
+    if ((st = query_core(mode, probe, acq, tx, ang, tref, grid, &c)) != WF_OK) return st;
+    *bytes = split_ws_bytes(c->sp, acq->n_frames, grid->nz, grid->nx);
     return ok();
 }
 
 // Workspace of the two-stage adjoint for one frame: every (transmit,
 // channel, tile) window (nst + 1 floats) and its first sample (int).
-size_t adjoint_ws_bytes(const wf_acq* acq, const TilePlan& tp) {
-    const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
+size_t adjoint_ws_bytes(const PlanCore& c) {
+    const TilePlan& tp = c.tp;
+    const size_t slots = (size_t)c.n_tx * c.n_ch * tp.ntz * tp.ntx;
     return slots * (size_t)(tp.nst + 1) * 4 + slots * 4 + 256 + 256;  // + max |g|
 }
 
@@ -870,26 +1089,24 @@ wf_status wf_das_adjoint_workspace(int32_t mode, const wf_probe* probe, const wf
                                    int32_t tref, const wf_grid* grid, uint64_t* bytes) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
     if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
-    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    const int32_t* tx = mode == 0 ? tx_elem : nullptr;
+    const double* ang = mode == 1 ? angles_rad : nullptr;
+    wf_status st = check_geometry(mode, probe, acq, tx, ang, tref, grid, true);
     if (st != WF_OK) return st;
-    Geometry g;
-    build_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                   mode == 1 ? angles_rad : nullptr, tref, grid, &g);
-    TilePlan tp;
-    if (!choose_tile(g, acq, grid, &tp))
-        return fail(WF_ERR_UNSUPPORTED, "pixel spacing too coarse for the DAS tile window");
-    *bytes = adjoint_ws_bytes(acq, tp);
+    std::shared_ptr<const PlanCore> c;
+    if ((st = query_core(mode, probe, acq, tx, ang, tref, grid, &c)) != WF_OK) return st;
+    *bytes = adjoint_ws_bytes(*c);
     return ok();
 }
 
 wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
                          const int32_t* tx_elem, const double* angles_rad, int32_t tref,
-                         const wf_grid* grid, const float* g, float* grad_rf, void* workspace,
-                         uint64_t workspace_bytes, void* stream) {
+                         const wf_grid* grid, const wf_plan* plan, const float* g, float* grad_rf,
+                         void* workspace, uint64_t workspace_bytes, void* stream) {
     if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
-    wf_status st = check_geometry(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                                  mode == 1 ? angles_rad : nullptr, tref, grid, true);
+    const int32_t* tx = mode == 0 ? tx_elem : nullptr;
+    const double* ang = mode == 1 ? angles_rad : nullptr;
+    wf_status st = check_geometry(mode, probe, acq, tx, ang, tref, grid, true);
     if (st != WF_OK) return st;
     if (acq->dtype != WF_RF_F32)
         return fail(WF_ERR_INVALID_ARG, "the RF gradient is float32 (acq->dtype=%d)", acq->dtype);
@@ -903,18 +1120,21 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     const size_t gbytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
     if (overlaps(g, gbytes, grad_rf, rf_bytes_of(acq)))
         return fail(WF_ERR_INVALID_ARG, "grad_rf overlaps g");
-    wf::DasArgs a;
-    TilePlan tp;
-    Geometry geo;
-    if ((st = prepare_das(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
-                          mode == 1 ? angles_rad : nullptr, tref, grid, &a, &tp, &geo)) != WF_OK)
+    std::unique_lock<std::mutex> lk;
+    Resolved r;
+    if ((st = resolve(mode, probe, acq, tx, ang, tref, grid, plan, (hipStream_t)stream, &lk,
+                      &r)) != WF_OK)
         return st;
-    const size_t need = adjoint_ws_bytes(acq, tp);
+    const TilePlan& tp = r.core->tp;
+    const SplitPlan& sp = r.core->sp;
+    const size_t need = adjoint_ws_bytes(*r.core);
     if (workspace_bytes < need)
         return fail(WF_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
                     (unsigned long long)workspace_bytes, (unsigned long long)need);
     if (overlaps(workspace, need, grad_rf, rf_bytes_of(acq)) || overlaps(workspace, need, g, gbytes))
         return fail(WF_ERR_INVALID_ARG, "workspace overlaps g or grad_rf");
+    wf::DasArgs a;
+    fill_args(*r.core, r.t, acq, grid, &a);
     const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
     a.ntiles = tp.ntz * tp.ntx;
     a.ws_win = static_cast<float*>(workspace);
@@ -926,7 +1146,6 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     // the forward's work split: items write disjoint windows, so the split
     // needs no partial sums; windows of items left out of the work list are
     // marked empty first (a fill kernel with kNoWindow's bit pattern)
-    const SplitPlan sp = plan_split(mode, geo, acq, grid, tp);
     a.nsplit = sp.nsplit;
     a.split_chunks = sp.chunks;
     a.nts = sp.nts;
@@ -934,7 +1153,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     const long long all_items = (long long)a.ntiles * sp.nsplit;
     const bool skipped = !sp.order.empty() && (long long)sp.order.size() < all_items;
     if (!sp.order.empty() && (sp.nsplit > 1 || skipped)) {
-        if ((st = device_items(sp, &a.items)) != WF_OK) return st;
+        a.items = r.t.items;
         a.nitems = (int)sp.order.size();
     }
     float no_window;
@@ -943,10 +1162,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     // one set of 8-byte G and H windows takes the bytes of the forward's two
     // buffers of 8-byte entries; a second set, where it fits, saves a
     // barrier per pass
-    const int nbuf = (WF_ADJ_TWO_SETS &&
-                      wf::das_lds(wf::das_adjoint_nbuf(2), tp.slot, acq->n_tx).total <= kLdsHard)
-                         ? 2
-                         : 1;
+    const int nbuf = adjoint_sets(tp, acq->n_tx);
     const size_t lds = wf::das_lds(wf::das_adjoint_nbuf(nbuf), tp.slot, acq->n_tx).total;
     const size_t frame_rf = (size_t)acq->n_tx * acq->n_ch * acq->n_s;
     for (int f = 0; f < acq->n_frames; ++f) {
@@ -968,6 +1184,109 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// plans in caller memory
+// ---------------------------------------------------------------------------
+
+static wf_status plan_bytes_common(int mode, const wf_probe* probe, const wf_acq* acq,
+                                   const int32_t* tx_elem, const double* angles, int32_t tref,
+                                   const wf_grid* grid, uint64_t* bytes) {
+    if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    if (st != WF_OK) return st;
+    PlanCore c;
+    if ((st = make_core(mode, probe, acq, tx_elem, angles, tref, grid, &c)) != WF_OK) return st;
+    *bytes = table_layout(c).total;
+    return ok();
+}
+
+static wf_status plan_build_common(int mode, const wf_probe* probe, const wf_acq* acq,
+                                   const int32_t* tx_elem, const double* angles, int32_t tref,
+                                   const wf_grid* grid, void* dev_mem, uint64_t bytes,
+                                   wf_plan** out, void* stream) {
+    if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    if (st != WF_OK) return st;
+    if (!dev_mem) return fail(WF_ERR_INVALID_ARG, "dev_mem is NULL");
+    if (((uintptr_t)dev_mem & (kTableAlign - 1)) != 0)
+        return fail(WF_ERR_INVALID_ARG, "dev_mem is not 256-byte aligned");
+    auto c = std::make_shared<PlanCore>();
+    if ((st = make_core(mode, probe, acq, tx_elem, angles, tref, grid, c.get())) != WF_OK)
+        return st;
+    const size_t need = table_layout(*c).total;
+    if (bytes < need)
+        return fail(WF_ERR_WORKSPACE, "plan memory of %llu bytes, %llu needed",
+                    (unsigned long long)bytes, (unsigned long long)need);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if ((st = prepare_kernels(*c, acq, grid)) != WF_OK) return st;
+    DevTables t;
+    if ((st = upload_tables(*c, dev_mem, (hipStream_t)stream, &t)) != WF_OK) return st;
+    wf_plan* p = new (std::nothrow) wf_plan;
+    if (!p) return fail(WF_ERR_DEVICE, "out of host memory for the plan handle");
+    p->magic = kPlanMagic;
+    p->core = std::move(c);
+    p->device = dev;
+    p->t = t;
+    *out = p;
+    return ok();
+}
+
+wf_status wf_plan_bytes_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                             const wf_grid* grid, uint64_t* bytes) {
+    return plan_bytes_common(0, probe, acq, tx_elem, nullptr, 0, grid, bytes);
+}
+
+wf_status wf_plan_bytes_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
+                            int32_t tref, const wf_grid* grid, uint64_t* bytes) {
+    return plan_bytes_common(1, probe, acq, nullptr, angles_rad, tref, grid, bytes);
+}
+
+wf_status wf_plan_build_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                             const wf_grid* grid, void* dev_mem, uint64_t bytes, wf_plan** out,
+                             void* stream) {
+    return plan_build_common(0, probe, acq, tx_elem, nullptr, 0, grid, dev_mem, bytes, out,
+                             stream);
+}
+
+wf_status wf_plan_build_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
+                            int32_t tref, const wf_grid* grid, void* dev_mem, uint64_t bytes,
+                            wf_plan** out, void* stream) {
+    return plan_build_common(1, probe, acq, nullptr, angles_rad, tref, grid, dev_mem, bytes, out,
+                             stream);
+}
+
+void wf_plan_destroy(wf_plan* plan) {
+    if (!plan || plan->magic != kPlanMagic) return;
+    plan->magic = 0;
+    delete plan;
+}
+
+wf_status wf_plan_workspace(const wf_plan* plan, int32_t n_frames, uint64_t* das_bytes,
+                            uint64_t* adjoint_bytes) {
+    if (!plan || plan->magic != kPlanMagic)
+        return fail(WF_ERR_INVALID_ARG, "plan is not a live wf_plan");
+    if (n_frames < 1 || n_frames > 65535)
+        return fail(WF_ERR_INVALID_ARG, "n_frames=%d outside [1, 65535]", n_frames);
+    if (!das_bytes || !adjoint_bytes)
+        return fail(WF_ERR_INVALID_ARG, "das_bytes and adjoint_bytes must not be NULL");
+    const PlanCore& c = *plan->core;
+    *das_bytes = split_ws_bytes(c.sp, n_frames, c.nz, c.nx);
+    *adjoint_bytes = adjoint_ws_bytes(c);
+    return ok();
+}
+
+wf_status wf_geometry_cache_info(uint64_t* entries, uint64_t* device_bytes) {
+    if (!entries || !device_bytes)
+        return fail(WF_ERR_INVALID_ARG, "entries and device_bytes must not be NULL");
+    std::lock_guard<std::mutex> lk(cache().mu);
+    *entries = cache().lru.size();
+    *device_bytes = cache().device_bytes;
+    return ok();
+}
+
 wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* stream) {
     if (!a || !b || !out) return fail(WF_ERR_INVALID_ARG, "a, b and out must not be NULL");
     if (n < 0) return fail(WF_ERR_INVALID_ARG, "n=%lld is negative", (long long)n);
@@ -983,25 +1302,24 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     wf_status st = check_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, true);
     if (st != WF_OK) return st;
     if (!info) return fail(WF_ERR_INVALID_ARG, "info is NULL");
-    Geometry g;
-    build_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, &g);
-    TilePlan tp;
-    if (!choose_tile(g, acq, grid, &tp))
-        return fail(WF_ERR_UNSUPPORTED,
-                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
-                    g.dzs, g.dxs);
+    std::shared_ptr<const PlanCore> c;
+    if ((st = query_core(mode, probe, acq, mode == 0 ? tx_elem : nullptr,
+                         mode == 1 ? angles_rad : nullptr, tref, grid, &c)) != WF_OK)
+        return st;
+    const TilePlan& tp = c->tp;
     info[0] = tp.px;
     info[1] = 1 << tp.tz_log2;
     info[2] = (tp.threads * tp.px) >> tp.tz_log2;
     info[3] = tp.span;
     info[4] = tp.nst;
     info[5] = tp.slot;
-    info[6] = (int32_t)das_gather_lds(tp, acq->n_tx, das_passes_per_barrier(tp, acq));
+    info[6] = (int32_t)das_gather_lds(tp, acq->n_tx,
+                                      das_passes_per_barrier(tp, acq->n_tx, acq->dtype));
     info[7] = tp.ntz;
     info[8] = tp.ntx;
     info[9] = wf::kChunk;
     info[10] = tp.threads;
-    const SplitPlan sp = plan_split(mode, g, acq, grid, tp);
+    const SplitPlan& sp = c->sp;
     const long long all_items = (long long)tp.ntz * tp.ntx * sp.nsplit;
     const bool listed = sp.nsplit > 1 ? !sp.order.empty()
                                       : !sp.order.empty() && (long long)sp.order.size() < all_items;
@@ -1022,10 +1340,21 @@ wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     if (st != WF_OK) return st;
     if (!tx_hi || !tx_lo || !rx_hi || !rx_lo)
         return fail(WF_ERR_INVALID_ARG, "an output pointer is NULL");
-    Geometry g;
-    CacheEntry ce;
-    st = device_tables(mode, probe, acq, tx_elem, angles_rad, tref, grid, &g, &ce);
-    if (st != WF_OK) return st;
+    // a verification call: the tables go to a temporary device buffer that
+    // is freed once the stream has run the kernel
+    PlanCore c;
+    build_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, &c.g);
+    const TableLayout L = table_layout(c);
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, L.total);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(delay tables)");
+    DevTables t;
+    st = upload_tables(c, mem, (hipStream_t)stream, &t);
+    if (st != WF_OK) {
+        (void)hipFree(mem);
+        return st;
+    }
+    const Geometry& g = c.g;
     wf::DelayArgs a{};
     a.tx_hi = tx_hi;
     a.tx_lo = tx_lo;
@@ -1039,10 +1368,14 @@ wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     a.dZ = g.dZ;
     a.dX = g.dX;
     a.O = g.O;
-    a.tx_tab = ce.tx;
-    a.ch_tab = ce.ch;
-    hipError_t e = wf::launch_delays(mode, a, (hipStream_t)stream);
+    a.tx_tab = t.tx;
+    a.ch_tab = t.ch;
+    e = wf::launch_delays(mode, a, (hipStream_t)stream);
+    hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
+    hipError_t e3 = hipFree(mem);
     if (e != hipSuccess) return hip_fail(e, "delay kernel launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "delay kernel");
+    if (e3 != hipSuccess) return hip_fail(e3, "hipFree(delay tables)");
     return ok();
 }
 
@@ -1154,18 +1487,15 @@ wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx,
 }
 
 wf_status wf_geometry_cache_clear(void) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    GeometryCache& gc = cache();
+    std::lock_guard<std::mutex> lk(gc.mu);
     hipError_t first = hipSuccess;
-    for (auto& kv : g_cache) {
-        hipError_t e = hipFree(kv.second.dev);
+    for (auto& kv : gc.lru) {
+        hipError_t e = free_uploads(kv.second);
         if (e != hipSuccess && first == hipSuccess) first = e;
     }
-    g_cache.clear();
-    for (auto& kv : g_items_cache) {
-        hipError_t e = hipFree(kv.second);
-        if (e != hipSuccess && first == hipSuccess) first = e;
-    }
-    g_items_cache.clear();
+    gc.lru.clear();
+    gc.index.clear();
     if (first != hipSuccess) return hip_fail(first, "hipFree(geometry table)");
     return ok();
 }

@@ -30,6 +30,12 @@
 //    reproducible run to run.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "das_common.h"
 
 namespace wf {
@@ -389,9 +395,7 @@ __global__ void __launch_bounds__(256) delays_kernel(const DelayArgs a) {
 
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
-    if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), lds);
 }
 
 template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG = 1, int PP = 1>
@@ -401,7 +405,7 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     if (a.pp != PP || !das_lds_fits(lds, das_gather_nbuf(PP), a.slot, a.T))
         return hipErrorInvalidValue;
     hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || a.prepare_only) return e;
     const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, groups, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), groups, (unsigned)a.nsplit);
@@ -465,8 +469,49 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Plan tables through kernel arguments: one word per lane.
+struct StoreWords {
+    uint32_t w[kStoreWords];
+};
+
+__global__ void __launch_bounds__(1024) store_kernel(uint32_t* __restrict__ dst, StoreWords src,
+                                                     int n) {
+    const int i = (int)threadIdx.x;
+    if (i < n) dst[i] = src.w[i];
+}
+
 }  // namespace
 
+hipError_t allow_dynamic_lds(const void* kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    if (lds > kLdsPerCu) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::set<std::pair<const void*, int>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({kernel, dev})) return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsPerCu);
+    if (e == hipSuccess) done.insert({kernel, dev});
+    return e;
+}
+
+hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const uint32_t* w = static_cast<const uint32_t*>(src);
+    uint32_t* d = static_cast<uint32_t*>(dst);
+    for (size_t done = 0, n = bytes / 4; done < n;) {
+        const int k = (int)std::min<size_t>(kStoreWords, n - done);
+        StoreWords sw{};
+        std::memcpy(sw.w, w + done, (size_t)k * 4);
+        hipLaunchKernelGGL(store_kernel, dim3(1), dim3(1024), 0, s, d + done, sw, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        done += (size_t)k;
+    }
+    return hipSuccess;
+}
 
 static bool shape_ok(int nt, int px, int groups) {
     if (nt == 1024 || nt == 512) return px == 2 && groups <= 2;

@@ -266,11 +266,8 @@ hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int w
     const int blocks = (mx + kMomCols - 1) / kMomCols;
     const size_t lds = 3 * sizeof(float) * (size_t)(min(kMomCols, mx) - 1) * sx +
                        3 * sizeof(float) * (size_t)wx;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(moments_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(moments_kernel), lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(moments_kernel, dim3((unsigned)mz, (unsigned)F, (unsigned)blocks),
                        dim3(kMomThreads), lds, s, env, out, nz, nx, wz, wx, sz, sx, mz, mx);
     return hipGetLastError();

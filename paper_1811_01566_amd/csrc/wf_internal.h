@@ -87,6 +87,8 @@ struct DasArgs {
     float* ws_win;      // adjoint workspace: window of (t, c, tile), nst + 1 samples
     int* ws_a0;         // adjoint workspace: first sample of that window or kNoWindow
     const float* ws_gmax;  // adjoint workspace: largest |g| of each launched frame
+    int prepare_only;   // 1: set the launch attributes of the kernel this call would
+                        // launch (its dynamic LDS limit) and launch nothing
 };
 
 struct DelayArgs {
@@ -105,6 +107,15 @@ struct FirTaps {
     float h[64];
 };
 
+// LDS of one gfx950 CU, the most one workgroup may take.
+constexpr size_t kLdsPerCu = 163840;
+
+// Raises the dynamic-LDS limit of `kernel` (a __global__ function's host
+// address) to kLdsPerCu on the current device when `lds` exceeds the
+// default 64 KB, once per kernel and device: later launches, including
+// those recorded into a graph, make no attribute call.
+hipError_t allow_dynamic_lds(const void* kernel, size_t lds);
+
 // Launchers; return the hipError_t of the launch.
 hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
                       size_t lds_bytes, hipStream_t s);
@@ -119,6 +130,11 @@ hipError_t launch_absmax(const float* g, size_t n, float* out, hipStream_t s);
 hipError_t launch_adjoint_reduce(const float* ws_win, const int* ws_a0, float* grad, int rows,
                                  int ntiles, int ne, int S, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+// Copies `bytes` (a multiple of 4) of host memory to device memory `dst`
+// through kernel arguments, in pieces of kStoreWords words: stream-ordered,
+// capturable into a graph, and the host buffer may be freed on return.
+constexpr int kStoreWords = 960;
+hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
 hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,

@@ -2,10 +2,11 @@
 
 Requests of different geometries (array size, transmit count, record length,
 pixel grid, STAI or PWI) arrive over time.  The service keeps, per shape
-class, resident executors: the geometry's constant table (cached by libwf),
-device buffers for one frame (RF in, beamformed RF, B-mode out, column
-maxima, the DAS work-split workspace) and a captured HIP graph of the whole path (DAS -> envelope -> log
-compression), replayed per request.  Up to ``n_streams`` requests are in
+class, resident executors: a plan of the geometry (delay tables and work
+list in device memory the executor owns), device buffers for one frame (RF
+in, beamformed RF, B-mode out, column maxima, the DAS work-split workspace)
+and a HIP graph of the whole path (DAS -> envelope -> log compression),
+captured on the executor's first call and replayed per request.  Up to ``n_streams`` requests are in
 flight at once, each on its own stream, so a request that arrives while
 others run is admitted as soon as a stream slot and memory are free, and its
 kernels overlap with theirs on the device.
@@ -36,7 +37,7 @@ import time
 from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional, Sequence
 
-from . import Scan, bmode, das, das_workspace_bytes
+from . import Plan, Scan, bmode, das, das_workspace_bytes, plan_bytes
 
 
 @dataclass
@@ -80,8 +81,9 @@ def frame_bytes(req: Request) -> int:
 
 
 class Executor:
-    """Buffers (and, with graphs, a captured replay) for one frame of one
-    shape class."""
+    """Plan, buffers and (with graphs) a captured replay for one frame of
+    one shape class.  The plan's device tables live as long as the executor
+    and its graph."""
 
     def __init__(self, req: Request, device, use_graph: bool):
         import torch
@@ -89,35 +91,29 @@ class Executor:
         g = req.scan.grid
         self.scan = req.scan
         self.dr_db = req.dr_db
+        self.plan = Plan(req.scan, req.n_s, device=device)
         self.rf = torch.zeros((1, req.scan.n_tx, req.scan.n_ch, req.n_s), dtype=torch.int16,
                               device=device)
         self.y = torch.empty((1, g.nz, g.nx), dtype=torch.float32, device=device)
         self.out = torch.empty_like(self.y)
         self.col_max = torch.empty((1, g.nx), dtype=torch.float32, device=device)
-        wsb = das_workspace_bytes(req.scan, req.n_s, 1)
+        wsb = self.plan.workspace_bytes(1)[0]
         self.ws = torch.empty(wsb, dtype=torch.uint8, device=device) if wsb else None
-        self.nbytes = frame_bytes(req) + wsb
+        self.nbytes = frame_bytes(req) + wsb + self.plan.mem.numel()
         self.graph = None
         self.busy = False
         self.last_used = 0.0
-        # warm-up outside any capture: uploads the geometry table and sets
-        # kernel attributes, so the captured calls only enqueue kernels
-        self._launch()
+        # the plan's tables were written on the current stream; with the
+        # plan the path only enqueues kernels, so its first call is captured
         torch.cuda.synchronize(device)
         if use_graph:
-            side = torch.cuda.Stream(device=device)
-            side.wait_stream(torch.cuda.current_stream(device))
-            with torch.cuda.stream(side):
-                self._launch()
-            torch.cuda.current_stream(device).wait_stream(side)
-            torch.cuda.synchronize(device)
             self.graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(self.graph):
                 self._launch()
             torch.cuda.synchronize(device)
 
     def _launch(self):
-        das(self.scan, self.rf, out=self.y, workspace=self.ws)
+        das(self.scan, self.rf, out=self.y, workspace=self.ws, plan=self.plan)
         bmode(self.y, self.dr_db, out=self.out, col_max=self.col_max)
 
     def run(self):
@@ -144,7 +140,8 @@ class GpuBackend:
         return Executor(req, self.device, self.use_graphs)
 
     def executor_bytes(self, req: Request) -> int:
-        return frame_bytes(req) + das_workspace_bytes(req.scan, req.n_s, 1)
+        return (frame_bytes(req) + das_workspace_bytes(req.scan, req.n_s, 1) +
+                plan_bytes(req.scan, req.n_s))
 
     def launch(self, ex: Executor, req: Request, stream):
         torch = self.torch

@@ -27,7 +27,10 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("wf_das_stai", "wf_das_pwi", "wf_envelope", "wf_bmode", "wf_log_compress",
-              "wf_delays", "wf_last_error", "wf_abi_version", "wf_geometry_cache_clear"):
+              "wf_delays", "wf_last_error", "wf_abi_version", "wf_geometry_cache_clear",
+              "wf_plan_bytes_stai", "wf_plan_bytes_pwi", "wf_plan_build_stai",
+              "wf_plan_build_pwi", "wf_plan_destroy", "wf_plan_workspace",
+              "wf_geometry_cache_info"):
         assert n in names, n
 
 
@@ -40,7 +43,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wf_abi_version() == 4
+    assert lib.wf_abi_version() == 5
 
 
 def _geom(n_elem=8, n_tx=4, n_ch=8, n_s=256):
@@ -72,33 +75,33 @@ FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
 def test_acq_validation(lib, field, value, code, needle):
     probe, acq, grid = _geom()
     setattr(acq, field, value)
-    st = lib.wf_das_stai(FAKE, probe, acq, None, grid, FAKE, None, 0, None)
+    st = lib.wf_das_stai(FAKE, probe, acq, None, grid, None, FAKE, None, 0, None)
     assert st == code
     assert needle in _err(lib)
 
 
 def test_null_and_alignment_errors(lib):
     probe, acq, grid = _geom()
-    assert lib.wf_das_stai(None, probe, acq, None, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_stai(None, probe, acq, None, grid, None, FAKE, None, 0, None) == -1
     assert "rf is NULL" in _err(lib)
-    assert lib.wf_das_stai(ctypes.c_void_p(0x10002), probe, acq, None, grid, FAKE, None, 0, None) == -2
+    assert lib.wf_das_stai(ctypes.c_void_p(0x10002), probe, acq, None, grid, None, FAKE, None, 0, None) == -2
     assert "16-byte" in _err(lib)
-    assert lib.wf_das_stai(FAKE, None, acq, None, grid, FAKE, None, 0, None) == -1
-    assert lib.wf_das_stai(FAKE, probe, acq, None, None, FAKE, None, 0, None) == -1
+    assert lib.wf_das_stai(FAKE, None, acq, None, grid, None, FAKE, None, 0, None) == -1
+    assert lib.wf_das_stai(FAKE, probe, acq, None, None, None, FAKE, None, 0, None) == -1
 
 
 def test_transmit_and_angle_validation(lib):
     probe, acq, grid = _geom()
     bad = (ctypes.c_int32 * 4)(0, 1, 2, 9)
-    assert lib.wf_das_stai(FAKE, probe, acq, bad, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_stai(FAKE, probe, acq, bad, grid, None, FAKE, None, 0, None) == -1
     assert "tx_elem[3]" in _err(lib)
     ang = (ctypes.c_double * 4)(0.0, 0.1, 1.5, 0.0)
-    assert lib.wf_das_pwi(FAKE, probe, acq, ang, 0, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_pwi(FAKE, probe, acq, ang, 0, grid, None, FAKE, None, 0, None) == -1
     assert "angles_rad[2]" in _err(lib)
     ok = (ctypes.c_double * 4)(0.0, 0.1, 0.2, 0.0)
-    assert lib.wf_das_pwi(FAKE, probe, acq, ok, 5, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_pwi(FAKE, probe, acq, ok, 5, grid, None, FAKE, None, 0, None) == -1
     assert "tref" in _err(lib)
-    assert lib.wf_das_pwi(FAKE, probe, acq, None, 0, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_pwi(FAKE, probe, acq, None, 0, grid, None, FAKE, None, 0, None) == -1
 
 
 def test_channel_map_validation(lib):
@@ -107,13 +110,13 @@ def test_channel_map_validation(lib):
     probe, acq, grid = _geom()
     rx = (ctypes.c_int32 * 8)(0, 1, 2, 3, 4, 5, 6, 8)
     acq.rx_elem = ctypes.cast(rx, _lib.c_int32_p)
-    assert lib.wf_das_stai(FAKE, probe, acq, None, grid, FAKE, None, 0, None) == -1
+    assert lib.wf_das_stai(FAKE, probe, acq, None, grid, None, FAKE, None, 0, None) == -1
     assert "rx_elem[7]" in _err(lib)
 
 
 def test_overlap_rejected(lib):
     probe, acq, grid = _geom()
-    assert lib.wf_das_stai(FAKE, probe, acq, None, grid, ctypes.c_void_p(0x10000 + 64), None, 0, None) == -1
+    assert lib.wf_das_stai(FAKE, probe, acq, None, grid, None, ctypes.c_void_p(0x10000 + 64), None, 0, None) == -1
     assert "overlaps" in _err(lib)
 
 

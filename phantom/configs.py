@@ -247,23 +247,17 @@ def served_mix(seed: int = 7) -> Sequence[Workload]:
     return out
 
 
-def served_pool(n_classes: int = 16, seed: int = 7, n_points: int = 24) -> Sequence[Workload]:
-    """A seeded subset of the served-mix shape classes, each with a sparse
-    point phantom (exact pulses) so that a pool of RF for every class is
-    quick to synthesise; the served stream draws its requests from it."""
+def served_pool(n_classes: int = 16, seed: int = 7) -> Sequence[Workload]:
+    """A seeded subset of the served-mix shape classes, each with its own
+    seeded speckle + cyst phantom (4000 Rayleigh scatterers, one 4 mm
+    anechoic cyst); the served stream draws its requests from one RF frame
+    per class."""
     import random
 
     mix = list(served_mix(seed))
     rnd = random.Random(seed)
     picks = rnd.sample(range(len(mix)), n_classes)
-    out = []
-    for k, i in enumerate(sorted(picks)):
-        w = mix[i]
-        pr = random.Random(seed * 1000 + i)
-        xs = tuple(pr.uniform(w.elem_x()[0], w.elem_x()[-1]) for _ in range(n_points))
-        zs = tuple(pr.uniform(6e-3, 29e-3) for _ in range(n_points))
-        out.append(w.with_(phantom="points", phantom_args=dict(x=xs, z=zs), seed=seed + k))
-    return out
+    return [mix[i].with_(seed=seed * 1000 + k) for k, i in enumerate(sorted(picks))]
 
 
 # qUS moment maps of the envelope: window 32 depth samples (about three pulse

@@ -70,6 +70,47 @@ def test_adjoint_matches_oracle_and_dot_product(wf_gpu, name):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+def test_adjoint_full_size_production_launch(wf_gpu):
+    """The adjoint of the full PWI frame (1024 x 512, 64 plane waves x 128
+    channels x 2048 samples) in its production launch: unsplit 1024-thread
+    tiles, two window sets, the 1.7 GB per-tile window workspace and the
+    stage-2 reduce over all 256 tiles.  The cotangent is non-zero on four
+    whole columns, whose transpose the oracle computes; every sample of the
+    [T][C][S] gradient is compared, and the dot-product identity ties it to
+    the forward gather at the same size."""
+    torch = _t()
+    w = phantom.get_workload("pwi")
+    scan = scan_from_workload(w)
+    info = wf_gpu.tile_info(scan, w.n_s, 1, 2)
+    assert info["threads"] == 1024 and info["nsplit"] == 1
+    assert info["workgroups"] == info["ntz"] * info["ntx"] == 256
+    plan = wf_gpu.Plan(scan, w.n_s)
+    adj_bytes = plan.workspace_bytes(1)[1]
+    assert adj_bytes > (1 << 30)
+    cols = np.array([0, 131, 256, 511])
+    rng = np.random.default_rng(17)
+    gc = rng.normal(size=(w.nz, len(cols)))
+    g = np.zeros((w.nz, w.nx), dtype=np.float32)
+    g[:, cols] = gc.astype(np.float32)
+    ws = torch.empty(adj_bytes, dtype=torch.uint8, device="cuda")
+    gr = wf_gpu.das_adjoint(scan, torch.from_numpy(g).cuda()[None], w.n_s, workspace=ws,
+                            plan=plan)
+    r = phantom.synth_rf(w)[0].astype(np.float32)
+    y = wf_gpu.das(scan, torch.from_numpy(r).cuda()[None], plan=plan)
+    torch.cuda.synchronize()
+    iz = np.repeat(np.arange(w.nz), len(cols)).reshape(w.nz, len(cols))
+    ix = np.tile(cols, (w.nz, 1))
+    ref = oracle.das_adjoint_workload(g[:, cols].astype(np.float64), w, iz, ix)
+    got = gr[0].cpu().numpy()
+    err = nl2(got, ref)
+    lhs = float(np.sum(y[0].cpu().numpy().astype(np.float64)[:, cols] * g[:, cols]))
+    rhs = float(np.sum(r.astype(np.float64) * got))
+    print(f"pwi full adjoint: nL2 {err:.2e} over {got.size} samples, dot-product rel "
+          f"{abs(lhs - rhs) / abs(lhs):.2e}, workspace {adj_bytes / 2**30:.2f} GiB")
+    assert err <= 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
 def _smooth_rf(w, seed=5):
     rng = np.random.default_rng(seed)
     s = np.arange(w.n_s)

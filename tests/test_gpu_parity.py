@@ -332,3 +332,32 @@ def test_das_record_limited_grid(wf_gpu):
         print(f"deep grid: nL2 {err:.2e}, dead rows {int(dead.sum())}")
         assert err <= NL2_TOL
         assert np.all(yc[dead] == 0.0)
+
+
+@pytest.mark.oracle_frames("pwi", "stai_full")
+@pytest.mark.parametrize("name", ["pwi", "stai_full"])
+def test_full_frame_bmode(wf_gpu, name):
+    """The whole full-size frame in the benchmark's launch configuration
+    (its work-split workspace, a plan): beamformed RF against the oracle's
+    whole frame, and the B-mode image against the oracle's, whose dB scale
+    takes the frame maximum (the clip of Sec. III) - over every pixel."""
+    import oracle_frames
+
+    torch = _torch()
+    w = phantom.get_workload(name)
+    scan = scan_from_workload(w)
+    plan = wf_gpu.Plan(scan, w.n_s)
+    wsb = plan.workspace_bytes(1)[0]
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    rf = phantom.synth_rf(w)
+    y = wf_gpu.das(scan, _gpu(rf), workspace=ws, plan=plan)
+    b = wf_gpu.bmode(y, w.dr_db)
+    torch.cuda.synchronize()
+    ref = oracle_frames.das_frame(w)
+    b_ref = oracle.bmode(ref, w.dr_db)
+    err = nl2(y[0].cpu().numpy(), ref)
+    d = np.abs(b[0].cpu().numpy() - b_ref)
+    print(f"{name} whole frame: DAS nL2 {err:.2e}, B-mode max |dB diff| {d.max():.2e} "
+          f"(p99 {np.percentile(d, 99):.1e}), split workspace {wsb} bytes")
+    assert err <= NL2_TOL
+    assert d.max() <= DB_TOL

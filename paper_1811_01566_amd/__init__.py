@@ -129,7 +129,22 @@ class _Keep:
         return ctypes.cast(a, ctypes.POINTER(ctype))
 
 
+def _check_lengths(scan: Scan):
+    """The library reads n_tx transmit entries, n_ch channel elements and
+    n_elem element positions from these host lists: shorter ones would be
+    read past their end."""
+    for name, seq, n in (("tx_elem", scan.tx_elem, scan.n_tx),
+                         ("angles_rad", scan.angles_rad, scan.n_tx),
+                         ("rx_elem", scan.rx_elem, scan.n_ch),
+                         ("elem_x", scan.elem_x, scan.n_elem)):
+        if seq is not None and len(seq) != n:
+            raise ValueError(f"scan.{name} has {len(seq)} entries, {n} expected")
+    if scan.mode == "pwi" and scan.angles_rad is None:
+        raise ValueError("a PWI scan needs angles_rad")
+
+
 def _structs(scan: Scan, keep: _Keep, n_frames=1, n_s=0, dtype=0):
+    _check_lengths(scan)
     probe = _lib.WfProbe(int(scan.n_elem), float(scan.pitch),
                          keep.arr(ctypes.c_double, scan.elem_x))
     acq = _lib.WfAcq(int(n_frames), int(scan.n_tx), int(scan.n_ch), int(n_s), int(dtype),

@@ -63,6 +63,19 @@ class Workload:
     snr_db: Optional[float] = None
     seed: int = 0
 
+    def __post_init__(self):
+        # the per-transmit and per-channel lists must describe every transmit
+        # and channel: the library reads n_tx angles (or elements) and n_ch
+        # channel elements
+        if self.mode == "pwi" and (self.angles_deg is None or len(self.angles_deg) != self.n_tx):
+            raise ValueError(f"{self.name}: {self.n_tx} plane waves need as many angles_deg")
+        if self.tx_elem is not None and len(self.tx_elem) != self.n_tx:
+            raise ValueError(f"{self.name}: tx_elem has {len(self.tx_elem)} entries, "
+                             f"n_tx={self.n_tx}")
+        if self.rx_elem is not None and len(self.rx_elem) != self.n_ch:
+            raise ValueError(f"{self.name}: rx_elem has {len(self.rx_elem)} entries, "
+                             f"n_ch={self.n_ch}")
+
     # ----- derived geometry -------------------------------------------------
     def elem_x(self) -> list:
         """Element lateral positions (m), centred uniform linear array."""

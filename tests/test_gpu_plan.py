@@ -119,7 +119,8 @@ def test_learning_c_adds_nothing_to_the_cache(wf_gpu):
     matches the oracle's analytic derivative."""
     torch = _t()
     w = phantom.tiny_pwi(n_elem=32, n_ch=32, n_tx=6, n_s=1024, nz=96, nx=40, z_min=6e-3,
-                         z_max=11e-3, phantom="random")
+                         z_max=11e-3, phantom="random",
+                         angles_deg=(-12.0, -7.0, -2.0, 0.0, 5.0, 9.0))
     base = scan_from_workload(w)
     rf_np = phantom.synth_rf(w)[0].astype(np.float32)
     rng = np.random.default_rng(4)

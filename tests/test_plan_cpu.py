@@ -118,3 +118,27 @@ def test_binding_plan_bytes_match_the_library():
                    angles_rad=tuple(np.radians(np.linspace(-16, 16, 16))))
     probe, acq, grid, ang = _pwi()
     assert wf.plan_bytes(scan, 2048) == _pwi_bytes(_lib.load(), probe, acq, grid, ang)
+
+
+def test_binding_refuses_lists_shorter_than_the_geometry():
+    """The library reads n_tx angles or transmit elements and n_ch channel
+    elements from host arrays: the binding refuses shorter lists instead of
+    letting the library read past them (a 6-transmit scan with 3 angles once
+    gave a different plan key on every call)."""
+    import paper_1811_01566_amd as wf
+    import phantom
+
+    grid = wf.Grid(64, 32, 5e-3, 1e-4, -4e-3, 2.5e-4)
+    pwi = wf.Scan(mode="pwi", n_elem=32, pitch=0.3e-3, c=1540.0, fs=50e6, n_tx=6, n_ch=32,
+                  grid=grid, angles_rad=(-0.2, 0.0, 0.15))
+    with pytest.raises(ValueError, match="angles_rad has 3 entries, 6 expected"):
+        wf.plan_bytes(pwi, 1024)
+    stai = wf.Scan(mode="stai", n_elem=32, pitch=0.3e-3, c=1540.0, fs=50e6, n_tx=4, n_ch=32,
+                   grid=grid, tx_elem=(0, 1, 2), rx_elem=tuple(range(32)))
+    with pytest.raises(ValueError, match="tx_elem has 3 entries"):
+        wf.das_workspace_bytes(stai, 1024)
+    with pytest.raises(ValueError, match="rx_elem"):
+        wf.plan_bytes(wf.Scan(mode="stai", n_elem=32, pitch=0.3e-3, c=1540.0, fs=50e6, n_tx=4,
+                              n_ch=32, grid=grid, rx_elem=tuple(range(31))), 1024)
+    with pytest.raises(ValueError, match="plane waves need as many angles_deg"):
+        phantom.tiny_pwi(n_tx=6)

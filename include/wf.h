@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 5
+#define WF_ABI_VERSION 6
 
 typedef enum {
     WF_OK = 0,
@@ -160,6 +160,32 @@ wf_status wf_das_pwi(const void* rf, const wf_probe* probe, const wf_acq* acq,
                      const double* angles_rad, int32_t tref, const wf_grid* grid,
                      const wf_plan* plan, float* out, void* workspace,
                      uint64_t workspace_bytes, void* stream);
+
+/*
+ * DAS (mode 0 = STAI with tx_elem, 1 = PWI with angles_rad and tref) that
+ * allocates nothing: for callers that cannot call hipMalloc or have the
+ * library do so - code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  rf, out and the geometry arguments are
+ * those of wf_das_stai / wf_das_pwi; the result equals theirs to FP32
+ * rounding (the same kernels; a grid that splits its tiles sums partial
+ * frames in the same order when they fit, see below).
+ *   Scratch: the geometry tables and the split's partial frames live in one
+ *   static device array of WF_NOALLOC_SCRATCH_BYTES on each GPU the library
+ *   runs on, held until the process ends.  Each call writes the tables on
+ *   `stream` before its DAS launch (kernel stores, no memset); partial
+ *   frames that do not fit beside them make the call run unsplit.
+ *   Geometries whose tables exceed the array give WF_ERR_UNSUPPORTED.
+ *   Every call on a GPU shares that GPU's array and leaves its contents for
+ *   the next: calls that overlap on one GPU (different streams, or threads
+ *   without ordering) race and must be serialised by the caller.
+ *   Host: the launch plan comes from a small host-memory cache (16
+ *   geometries); the call allocates no device memory, frees none and never
+ *   synchronises.
+ */
+#define WF_NOALLOC_SCRATCH_BYTES (16u << 20)
+wf_status wf_das_noalloc(int32_t mode, const void* rf, const wf_probe* probe,
+                         const wf_acq* acq, const int32_t* tx_elem, const double* angles_rad,
+                         int32_t tref, const wf_grid* grid, float* out, void* stream);
 
 /*
  * Bytes of the optional workspace of wf_das_stai / wf_das_pwi / wf_das_dydc

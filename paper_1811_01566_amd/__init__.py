@@ -27,7 +27,7 @@ from ._lib import WfError, load
 __all__ = ["Grid", "Scan", "Plan", "das", "das_stai", "das_pwi", "delays", "envelope",
            "log_compress", "bmode", "load", "WfError", "abi_version", "geometry_cache_clear",
            "geometry_cache_info", "plan_bytes", "tile_info", "adjoint_workspace_bytes", "das_workspace_bytes",
-           "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd"]
+           "das_dydc", "das_adjoint", "dot", "DASFunction", "das_autograd", "das_noalloc"]
 
 
 @dataclass(frozen=True)
@@ -334,6 +334,32 @@ def das(scan: Scan, rf, out=None, workspace=None, stream=None, plan: Optional[Pl
         _lib.check(lib.wf_das_pwi(rfp, probe, acq, ang, _tref(scan), grid, ph, outp, wsp, wsb,
                                   st), "wf_das_pwi")
     del ws_keep  # the caching allocator keeps the block until the stream is done with it
+    out = out.view(nf, g.nz, g.nx)
+    return out[0] if squeeze else out
+
+
+def das_noalloc(scan: Scan, rf, out=None, stream=None):
+    """:func:`das` through ``wf_das_noalloc``: the library allocates no device
+    memory for the call (its geometry tables and split partial frames live
+    in a static per-GPU scratch array); overlapping calls on one GPU race."""
+    torch = _torch()
+    lib = load()
+    squeeze = rf.dim() == 3
+    rf4 = rf.unsqueeze(0) if squeeze else rf
+    nf, nt, nc, ns = rf4.shape
+    if nt != scan.n_tx or nc != scan.n_ch:
+        raise ValueError(f"rf shape {tuple(rf.shape)} does not match n_tx={scan.n_tx}, "
+                         f"n_ch={scan.n_ch}")
+    g = scan.grid
+    if out is None:
+        out = torch.empty((nf, g.nz, g.nx), dtype=torch.float32, device=rf.device)
+    elif out.dtype != torch.float32 or out.numel() != nf * g.nz * g.nx:
+        raise ValueError("out must be float32 with F*nz*nx elements")
+    keep = _Keep()
+    probe, acq, grid = _structs(scan, keep, nf, ns, _rf_dtype(rf4))
+    mode, tx, ang, tref = _mode_args(scan, keep)
+    _lib.check(lib.wf_das_noalloc(mode, _dev(rf4, "rf"), probe, acq, tx, ang, tref, grid,
+                                  _dev(out, "out"), _stream_ptr(rf4, stream)), "wf_das_noalloc")
     out = out.view(nf, g.nz, g.nx)
     return out[0] if squeeze else out
 

@@ -13,7 +13,7 @@ WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
 WF_ERR_WORKSPACE = -4
-WF_ABI_VERSION = 5
+WF_ABI_VERSION = 6
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2
 WF_PWI_TREF_FIRST, WF_PWI_TREF_CENTRE = 0, 1
@@ -59,6 +59,8 @@ SIGNATURES = {
                              c_int32_p]),
     "wf_das_dydc": (I, [I, V, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
                         V, ctypes.c_uint64, V]),
+    "wf_das_noalloc": (I, [I, V, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V,
+                           V]),
     "wf_das_adjoint": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
                            V, V, ctypes.c_uint64, V]),
     "wf_plan_bytes_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid),

@@ -30,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwf.so")
-SOURCES = ["api.cpp", "das.hip", "adjoint.hip", "envelope.hip", "prefilter.hip"]
+SOURCES = ["api.cpp", "das.hip", "adjoint.hip", "envelope.hip", "prefilter.hip", "noalloc.hip"]
 ARCH = os.environ.get("WF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -948,27 +948,30 @@ void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const w
     a->ch_tab = t.ch;
 }
 
-wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, const wf_acq* acq,
-                     const int32_t* tx_elem, const double* angles, int32_t tref,
-                     const wf_grid* grid, const wf_plan* plan, float* out, void* workspace,
-                     uint64_t ws_bytes, void* stream) {
-    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+// Checks of the buffers of a DAS-shaped call (after check_geometry).
+wf_status check_das_buffers(const void* rf, const wf_acq* acq, const wf_grid* grid,
+                            const float* out) {
+    wf_status st = check_rf(rf, acq);
     if (st != WF_OK) return st;
-    if ((st = check_rf(rf, acq)) != WF_OK) return st;
     if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
     if (((uintptr_t)out & 3) != 0) return fail(WF_ERR_INVALID_ARG, "out is not 4-byte aligned");
     const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
     if (overlaps(rf, rf_bytes_of(acq), out, out_bytes))
         return fail(WF_ERR_INVALID_ARG, "out overlaps rf");
-    std::unique_lock<std::mutex> lk;
-    Resolved r;
-    if ((st = resolve(mode, probe, acq, tx_elem, angles, tref, grid, plan, (hipStream_t)stream,
-                      &lk, &r)) != WF_OK)
-        return st;
-    const TilePlan& tp = r.core->tp;
-    const SplitPlan& sp = r.core->sp;
+    return WF_OK;
+}
+
+// The launches of a validated DAS-shaped call (op 0: value, 1: d y / d c)
+// with the host plan `core` and its device tables `t`: the split runs when
+// the workspace holds its partial frames.
+wf_status launch_gather(int mode, int op, const void* rf, const wf_acq* acq, const wf_grid* grid,
+                        const PlanCore& core, const DevTables& t, float* out, void* workspace,
+                        uint64_t ws_bytes, hipStream_t stream) {
+    const TilePlan& tp = core.tp;
+    const SplitPlan& sp = core.sp;
+    const size_t out_bytes = (size_t)acq->n_frames * grid->nz * grid->nx * 4;
     wf::DasArgs a;
-    fill_args(*r.core, r.t, acq, grid, &a);
+    fill_args(core, t, acq, grid, &a);
     a.rf = rf;
     a.out = out;
     const size_t need = split_ws_bytes(sp, acq->n_frames, grid->nz, grid->nx);
@@ -994,12 +997,12 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
                               : sp.nsplit == 1 && !sp.order.empty() &&
                                     (long long)sp.order.size() < all_items;
     if (listed) {
-        a.items = r.t.items;
+        a.items = t.items;
         a.nitems = (int)sp.order.size();
         if ((long long)sp.order.size() < all_items) {
             float* clear = split ? a.partial : out;
             const size_t n = (split ? (size_t)sp.nsplit : 1) * (out_bytes / 4);
-            hipError_t e = wf::launch_fill(clear, n, 0.0f, (hipStream_t)stream);
+            hipError_t e = wf::launch_fill(clear, n, 0.0f, stream);
             if (e != hipSuccess) return hip_fail(e, "fill launch");
         }
     }
@@ -1008,13 +1011,65 @@ wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, co
     a.pp = das_passes_per_barrier(tp, acq->n_tx, acq->dtype);
     const size_t lds = das_gather_lds(tp, acq->n_tx, a.pp);
     hipError_t e = op == 0 ? wf::launch_das(mode, acq->dtype, tp.threads, tp.px,
-                                            groups_of(a, tp), a, lds, (hipStream_t)stream)
+                                            groups_of(a, tp), a, lds, stream)
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
-                                                 groups_of(a, tp), a, lds, (hipStream_t)stream);
+                                                 groups_of(a, tp), a, lds, stream);
     if (e == hipSuccess && a.partial)
-        e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, (hipStream_t)stream);
+        e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, stream);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "DAS kernel launch" : "dy/dc kernel launch");
     return ok();
+}
+
+wf_status das_common(int mode, int op, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                     const int32_t* tx_elem, const double* angles, int32_t tref,
+                     const wf_grid* grid, const wf_plan* plan, float* out, void* workspace,
+                     uint64_t ws_bytes, void* stream) {
+    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    if (st != WF_OK) return st;
+    if ((st = check_das_buffers(rf, acq, grid, out)) != WF_OK) return st;
+    std::unique_lock<std::mutex> lk;
+    Resolved r;
+    if ((st = resolve(mode, probe, acq, tx_elem, angles, tref, grid, plan, (hipStream_t)stream,
+                      &lk, &r)) != WF_OK)
+        return st;
+    return launch_gather(mode, op, rf, acq, grid, *r.core, r.t, out, workspace, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+// Host plans of the static-scratch entry point: a small least-recently-used
+// list in host memory only.  It holds no device tables, so dropping an entry
+// frees no device memory.
+struct HostPlans {
+    std::mutex mu;
+    std::list<std::shared_ptr<const PlanCore>> lru;  // most recent first
+};
+
+HostPlans& host_plans() {
+    static HostPlans* h = new HostPlans;  // never destroyed: no teardown order issue
+    return *h;
+}
+
+constexpr size_t kHostPlans = 16;
+
+wf_status host_plan(int mode, const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
+                    const double* angles, int32_t tref, const wf_grid* grid,
+                    std::shared_ptr<const PlanCore>* out) {
+    auto c = std::make_shared<PlanCore>();
+    begin_core(mode, probe, acq, tx_elem, angles, tref, grid, c.get());
+    HostPlans& hp = host_plans();
+    std::lock_guard<std::mutex> lk(hp.mu);
+    for (auto it = hp.lru.begin(); it != hp.lru.end(); ++it)
+        if ((*it)->key == c->key) {
+            hp.lru.splice(hp.lru.begin(), hp.lru, it);
+            *out = hp.lru.front();
+            return WF_OK;
+        }
+    wf_status st = plan_core(acq, grid, c.get());
+    if (st != WF_OK) return st;
+    if (hp.lru.size() >= kHostPlans) hp.lru.pop_back();
+    hp.lru.push_front(c);
+    *out = c;
+    return WF_OK;
 }
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -1029,6 +1084,40 @@ wf_status check_image(const float* a, int F, int nz, int nx, const char* name) {
 }
 
 }  // namespace
+
+namespace wf {
+
+wf_status report_hip(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+wf_status das_scratch(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                      const wf_grid* grid, float* out, wf_status (*get_scratch)(void**),
+                      size_t scratch_bytes, hipStream_t stream) {
+    if (mode != 0 && mode != 1) return fail(WF_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    const int32_t* tx = mode == 0 ? tx_elem : nullptr;
+    const double* ang = mode == 1 ? angles_rad : nullptr;
+    wf_status st = check_geometry(mode, probe, acq, tx, ang, tref, grid, true);
+    if (st != WF_OK) return st;
+    if ((st = check_das_buffers(rf, acq, grid, out)) != WF_OK) return st;
+    std::shared_ptr<const PlanCore> core;
+    if ((st = host_plan(mode, probe, acq, tx, ang, tref, grid, &core)) != WF_OK) return st;
+    const size_t tables = table_layout(*core).total;
+    if (tables > scratch_bytes)
+        return fail(WF_ERR_UNSUPPORTED,
+                    "the geometry tables take %llu bytes, more than the %llu-byte static scratch",
+                    (unsigned long long)tables, (unsigned long long)scratch_bytes);
+    // tables first, then the split's partial frames where they fit (the
+    // call runs unsplit otherwise)
+    void* scratch = nullptr;
+    if ((st = get_scratch(&scratch)) != WF_OK) return st;
+    DevTables t;
+    if ((st = upload_tables(*core, scratch, stream, &t)) != WF_OK) return st;
+    char* ws = static_cast<char*>(scratch) + tables;
+    return launch_gather(mode, 0, rf, acq, grid, *core, t, out, ws, scratch_bytes - tables,
+                         stream);
+}
+
+}  // namespace wf
 
 extern "C" {
 

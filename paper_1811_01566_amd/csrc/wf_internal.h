@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/wf.h"
 #include "das_layout.h"
 
 namespace wf {
@@ -143,6 +144,18 @@ hipError_t launch_log_compress(const float* env, const float* col_max, int F, in
                                float dr_db, int offset, float* out, hipStream_t s);
 hipError_t launch_fir(int dtype, const void* rf, long long n_rec, int S, int kp,
                       const FirTaps& taps, float* out, hipStream_t s);
+// DAS into caller buffers with the geometry tables, and the split's partial
+// frames where they fit, in a scratch block of scratch_bytes of device
+// memory that get_scratch returns once the arguments are validated (and
+// that stays valid for the call's work on `stream`); mode 0 STAI, 1 PWI.
+// Allocates and frees no device memory.
+wf_status das_scratch(int32_t mode, const void* rf, const wf_probe* probe, const wf_acq* acq,
+                      const int32_t* tx_elem, const double* angles_rad, int32_t tref,
+                      const wf_grid* grid, float* out, wf_status (*get_scratch)(void**),
+                      size_t scratch_bytes, hipStream_t stream);
+// Sets the calling thread's error message for a failed HIP call.
+wf_status report_hip(hipError_t e, const char* what);
+
 hipError_t launch_moments(const float* env, int F, int nz, int nx, int wz, int wx, int sz,
                           int sx, int mz, int mx, float* out, hipStream_t s);
 

@@ -43,7 +43,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wf_abi_version() == 5
+    from paper_1811_01566_amd import _lib
+
+    assert lib.wf_abi_version() == _lib.WF_ABI_VERSION == 6
 
 
 def _geom(n_elem=8, n_tx=4, n_ch=8, n_s=256):
@@ -146,3 +148,22 @@ def test_binding_refuses_cpu_tensors():
     rf = torch.zeros((2, 8, 256), dtype=torch.int16)
     with pytest.raises(ValueError, match="GPU"):
         wf.das(scan, rf)
+
+
+def test_noalloc_checks_arguments_before_the_device(lib):
+    """wf_das_noalloc validates like wf_das_pwi / wf_das_stai before it looks
+    up its scratch or touches the device."""
+    probe, acq, grid = _geom()
+    ang = (ctypes.c_double * 4)(-0.1, 0.0, 0.05, 0.1)
+    rf = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(0x8000000)
+    assert lib.wf_das_noalloc(2, rf, probe, acq, None, ang, 0, grid, out, None) == -1
+    assert "mode" in _err(lib)
+    assert lib.wf_das_noalloc(1, None, probe, acq, None, ang, 0, grid, out, None) == -1
+    assert "rf is NULL" in _err(lib)
+    assert lib.wf_das_noalloc(1, rf, probe, acq, None, ang, 0, grid, None, None) == -1
+    assert "out is NULL" in _err(lib)
+    assert lib.wf_das_noalloc(1, rf, probe, acq, None, None, 0, grid, out, None) == -1
+    acq.n_s = 250
+    assert lib.wf_das_noalloc(0, rf, probe, acq, None, None, 0, grid, out, None) == -2
+    assert "multiple of 8" in _err(lib)

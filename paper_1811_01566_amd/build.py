@@ -52,15 +52,38 @@ def compile_cmd(out: str) -> list:
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    tmp = out + f".tmp{os.getpid()}"
-    cmd = compile_cmd(tmp) + [f"-D{d}" for d in defines]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError(f"hipcc failed with status {r.returncode}")
-    os.replace(tmp, out)
+    """Every source compiled to an object in parallel (each carries its own
+    device code; no kernel calls across files), then one shared link."""
+    import tempfile
+
+    flags = compile_cmd("unused")
+    cc, opts = flags[0], [f for f in flags[1:] if f not in ("-shared", "-o", "unused")
+                          and not f.endswith((".cpp", ".hip"))]
+    opts += [f"-D{d}" for d in defines]
+    with tempfile.TemporaryDirectory() as tmpd:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, src + ".o")
+            objs.append(obj)
+            cmd = [cc, *opts, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                          text=True))
+        for p in procs:
+            log = p.communicate()[0]
+            if p.returncode != 0:
+                sys.stderr.write(log)
+                raise RuntimeError(f"hipcc failed with status {p.returncode}: {' '.join(p.args)}")
+        tmp = out + f".tmp{os.getpid()}"
+        link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        r = subprocess.run(link, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc link failed with status {r.returncode}")
+        os.replace(tmp, out)
     return out
 
 

@@ -46,8 +46,10 @@
  * geometry never run before.  With plan = NULL the library keeps the tables
  * in a cache of its own: the first call of a geometry on a device
  * allocates them (hipMalloc), writes them on `stream` and synchronises
- * `stream`; the cache holds at most 64 geometries and evicting the least
- * recently used one synchronises its device before freeing it.  Such calls
+ * `stream`; the cache holds at most 64 geometries and at most 4 GiB of
+ * device memory, gives an entry the delay tables of WF_PLAN_DELAY_TABLES
+ * when they take at most 512 MiB, and evicting the least recently used
+ * entry synchronises its device before freeing it.  Such calls
  * must not be captured into graphs (a graph would keep pointers the cache
  * may free); calls without a plan are serialised by a library lock from
  * the table lookup to their last launch.
@@ -68,7 +70,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 6
+#define WF_ABI_VERSION 7
 
 typedef enum {
     WF_OK = 0,
@@ -357,8 +359,17 @@ wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx,
  * every delay table and the launch plan of the DAS calls).
  *
  * wf_plan_bytes_stai / wf_plan_bytes_pwi: device bytes of the plan of this
- * geometry (host only, touches no device).  acq->n_frames and acq->dtype
- * must be valid but do not enter the plan.
+ * geometry built with `flags` (host only, touches no device).
+ * acq->n_frames and acq->dtype must be valid but do not enter the plan.
+ *
+ * flags: 0 or WF_PLAN_DELAY_TABLES.  With it the plan also holds the
+ * window-local fixed-point delays the gathers use (Sec. II-B: the time of
+ * flight of every pixel to every receive element and, for STAI, from every
+ * transmit element), formed once on the device at build time: 4 bytes per
+ * (pixel slot, channel) plus, for STAI, per (pixel slot, transmit) - about
+ * 256 MiB for 128 channels on a 1024 x 512 grid.  The DAS and d y / d c
+ * gathers then read those words instead of forming them, with bitwise the
+ * same results.  Other flag bits are refused (WF_ERR_INVALID_ARG).
  *
  * wf_plan_build_stai / wf_plan_build_pwi: computes the launch plan on the
  * host and writes the device tables into dev_mem (DEVICE, caller-owned,
@@ -376,16 +387,17 @@ wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx,
  * memory stays the caller's.  Work already enqueued with the plan keeps
  * reading dev_mem, not the handle.
  */
+#define WF_PLAN_DELAY_TABLES 1
 wf_status wf_plan_bytes_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
-                             const wf_grid* grid, uint64_t* bytes);
+                             const wf_grid* grid, int32_t flags, uint64_t* bytes);
 wf_status wf_plan_bytes_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
-                            int32_t tref, const wf_grid* grid, uint64_t* bytes);
+                            int32_t tref, const wf_grid* grid, int32_t flags, uint64_t* bytes);
 wf_status wf_plan_build_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
-                             const wf_grid* grid, void* dev_mem, uint64_t bytes, wf_plan** out,
-                             void* stream);
+                             const wf_grid* grid, int32_t flags, void* dev_mem, uint64_t bytes,
+                             wf_plan** out, void* stream);
 wf_status wf_plan_build_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
-                            int32_t tref, const wf_grid* grid, void* dev_mem, uint64_t bytes,
-                            wf_plan** out, void* stream);
+                            int32_t tref, const wf_grid* grid, int32_t flags, void* dev_mem,
+                            uint64_t bytes, wf_plan** out, void* stream);
 void wf_plan_destroy(wf_plan* plan);
 
 /* Workspace bytes of calls made with `plan` (host only): the DAS / d y / d c

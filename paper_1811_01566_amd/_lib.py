@@ -13,7 +13,8 @@ WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
 WF_ERR_WORKSPACE = -4
-WF_ABI_VERSION = 6
+WF_ABI_VERSION = 7
+WF_PLAN_DELAY_TABLES = 1  # plan flag: window-local delay tables in the plan
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2
 WF_PWI_TREF_FIRST, WF_PWI_TREF_CENTRE = 0, 1
@@ -63,13 +64,13 @@ SIGNATURES = {
                            V]),
     "wf_das_adjoint": (I, [I, P(WfProbe), P(WfAcq), c_int32_p, c_double_p, I, P(WfGrid), V, V,
                            V, V, ctypes.c_uint64, V]),
-    "wf_plan_bytes_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid),
+    "wf_plan_bytes_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), I,
                                ctypes.POINTER(ctypes.c_uint64)]),
-    "wf_plan_bytes_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid),
+    "wf_plan_bytes_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), I,
                               ctypes.POINTER(ctypes.c_uint64)]),
-    "wf_plan_build_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), V, ctypes.c_uint64,
-                               ctypes.POINTER(V), V]),
-    "wf_plan_build_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), V,
+    "wf_plan_build_stai": (I, [P(WfProbe), P(WfAcq), c_int32_p, P(WfGrid), I, V,
+                               ctypes.c_uint64, ctypes.POINTER(V), V]),
+    "wf_plan_build_pwi": (I, [P(WfProbe), P(WfAcq), c_double_p, I, P(WfGrid), I, V,
                               ctypes.c_uint64, ctypes.POINTER(V), V]),
     "wf_plan_destroy": (None, [V]),
     "wf_plan_workspace": (I, [V, I, ctypes.POINTER(ctypes.c_uint64),

@@ -339,7 +339,9 @@ hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
 
 template <int MODE, int NB>
 hipError_t launch_adj_nb(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024) return launch_adj<MODE, 1024, 2, NB>(a, lds, s);
+    if (nt == 1024)
+        return px == 1 ? launch_adj<MODE, 1024, 1, NB>(a, lds, s)
+                       : launch_adj<MODE, 1024, 2, NB>(a, lds, s);
     if (nt == 512) return launch_adj<MODE, 512, 2, NB>(a, lds, s);
     return px == 4 ? launch_adj<MODE, 256, 4, NB>(a, lds, s)
                    : launch_adj<MODE, 256, 1, NB>(a, lds, s);

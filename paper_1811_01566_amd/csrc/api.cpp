@@ -253,8 +253,13 @@ constexpr size_t kLdsHard = 163840;
 
 bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
     // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
-    // with twice the waves per workgroup, 1024 x 2 twice the tile
-    const int shapes[4][2] = {{WF_DAS_ALLOW_1024 ? 1024 : 512, 2}, {512, 2}, {256, 4}, {256, 1}};
+    // with twice the waves per workgroup, 1024 x 1 the same with four times
+    // the waves, 1024 x 2 twice the tile
+    const int shapes[5][2] = {{WF_DAS_ALLOW_1024 ? 1024 : 512, 2},
+                              {WF_DAS_ALLOW_1024 ? 1024 : 512, WF_DAS_ALLOW_1024 ? 1 : 2},
+                              {512, 2},
+                              {256, 4},
+                              {256, 1}};
     // a plan must leave LDS for 8 resident waves per CU (two 256-thread
     // workgroups, or one of 512 or 1024 threads); one with 4 is taken only
     // when nothing else fits
@@ -634,33 +639,56 @@ wf_status make_core(int mode, const wf_probe* probe, const wf_acq* acq, const in
 }
 
 // Device tables of a plan, inside one block of device memory:
-// [TxConst x T][ChConst x C][int x work-list items], each part 256-byte
-// aligned.
+// [TxConst x T][ChConst x C][int x work-list items] and, in plans built with
+// delay tables, [receive delay words][STAI transmit delay words]; each part
+// 256-byte aligned.
 struct DevTables {
     const wf::TxConst* tx = nullptr;
     const wf::ChConst* ch = nullptr;
-    const int* items = nullptr;  // null when the plan has no work list
+    const int* items = nullptr;       // null when the plan has no work list
+    const uint32_t* rx_q = nullptr;   // receive delay table (null: none)
+    const uint32_t* tx_q = nullptr;   // STAI transmit delay table (null: none)
 };
 
 constexpr size_t kTableAlign = 256;
 size_t align_up(size_t v) { return (v + kTableAlign - 1) & ~(kTableAlign - 1); }
 
 struct TableLayout {
-    size_t ch, items, total;
+    size_t ch, items, rx, tx, total;
 };
 
-TableLayout table_layout(const PlanCore& c) {
+void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
+               wf::DasArgs* a);
+
+// Words of the delay tables (DasArgs::rx_tab, tx_tabq): per tile and pixel
+// slot, 16 receive words per channel chunk and, for STAI, one transmit word
+// per transmit.
+size_t rx_table_words(const PlanCore& c) {
+    const size_t tiles = (size_t)c.tp.ntz * c.tp.ntx;
+    const size_t nch = (size_t)(c.n_ch + wf::kChunk - 1) / wf::kChunk;
+    return tiles * nch * (size_t)c.tp.threads * c.tp.px * wf::kChunk;
+}
+size_t tx_table_words(const PlanCore& c) {
+    if (c.mode != 0) return 0;
+    return (size_t)c.tp.ntz * c.tp.ntx * c.n_tx * (size_t)c.tp.threads * c.tp.px;
+}
+
+TableLayout table_layout(const PlanCore& c, bool delay_tables) {
     TableLayout L;
     L.ch = align_up(c.g.tx.size() * sizeof(wf::TxConst));
     L.items = align_up(L.ch + c.g.ch.size() * sizeof(wf::ChConst));
-    L.total = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
+    L.rx = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
+    L.tx = L.rx + (delay_tables ? align_up(rx_table_words(c) * 4) : 0);
+    L.total = L.tx + (delay_tables ? align_up(tx_table_words(c) * 4) : 0);
     return L;
 }
 
 // Writes the tables into `mem` (at least table_layout().total bytes) with
-// kernel launches on `s`: stream-ordered, and capturable.
-wf_status upload_tables(const PlanCore& c, void* mem, hipStream_t s, DevTables* out) {
-    const TableLayout L = table_layout(c);
+// kernel launches on `s`: stream-ordered, and capturable.  The delay
+// tables come from a kernel that forms the gathers' own words.
+wf_status upload_tables(const PlanCore& c, void* mem, bool delay_tables, const wf_acq* acq,
+                        const wf_grid* grid, hipStream_t s, DevTables* out) {
+    const TableLayout L = table_layout(c, delay_tables);
     char* m = static_cast<char*>(mem);
     hipError_t e = wf::launch_store(m, c.g.tx.data(), c.g.tx.size() * sizeof(wf::TxConst), s);
     if (e == hipSuccess)
@@ -668,9 +696,21 @@ wf_status upload_tables(const PlanCore& c, void* mem, hipStream_t s, DevTables* 
     if (e == hipSuccess && !c.sp.order.empty())
         e = wf::launch_store(m + L.items, c.sp.order.data(), c.sp.order.size() * sizeof(int), s);
     if (e != hipSuccess) return hip_fail(e, "plan table upload");
-    out->tx = reinterpret_cast<const wf::TxConst*>(m);
-    out->ch = reinterpret_cast<const wf::ChConst*>(m + L.ch);
-    out->items = c.sp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.items);
+    DevTables t;
+    t.tx = reinterpret_cast<const wf::TxConst*>(m);
+    t.ch = reinterpret_cast<const wf::ChConst*>(m + L.ch);
+    t.items = c.sp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.items);
+    if (delay_tables) {
+        uint32_t* rx = reinterpret_cast<uint32_t*>(m + L.rx);
+        uint32_t* tx = tx_table_words(c) ? reinterpret_cast<uint32_t*>(m + L.tx) : nullptr;
+        wf::DasArgs a;
+        fill_args(c, t, acq, grid, &a);
+        e = wf::launch_delay_tables(c.mode, c.tp.threads, c.tp.px, a, rx, tx, s);
+        if (e != hipSuccess) return hip_fail(e, "delay table kernel launch");
+        t.rx_q = rx;
+        t.tx_q = tx;
+    }
+    *out = t;
     return WF_OK;
 }
 
@@ -692,9 +732,6 @@ int adjoint_sets(const TilePlan& tp, int T) {
                ? 2
                : 1;
 }
-
-void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
-               wf::DasArgs* a);
 
 // Sets the dynamic-LDS limit of every kernel a plan can launch (each RF
 // type, single frames and batches, value and d y / d c gathers, the
@@ -811,10 +848,21 @@ wf_status cached_core(int mode, const wf_probe* probe, const wf_acq* acq, const 
     return WF_OK;
 }
 
+// Delay tables in cache entries: an entry gets them when they take at most
+// WF_CACHE_DELAY_TABLE_MAX bytes, and the cache evicts least recently used
+// entries to keep its device memory within WF_CACHE_DEVICE_BUDGET.
+#ifndef WF_CACHE_DELAY_TABLE_MAX
+#define WF_CACHE_DELAY_TABLE_MAX (512ull << 20)
+#endif
+#ifndef WF_CACHE_DEVICE_BUDGET
+#define WF_CACHE_DEVICE_BUDGET (4ull << 30)
+#endif
+
 // Device tables of a cached entry on the current device: allocated and
 // uploaded on first use, then `s` is synchronised so that calls on other
 // streams may read them (lock held by the caller).
-wf_status cached_tables(CacheEntry& ce, hipStream_t s, DevTables* out) {
+wf_status cached_tables(CacheEntry& ce, const wf_acq* acq, const wf_grid* grid, hipStream_t s,
+                        DevTables* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -825,10 +873,25 @@ wf_status cached_tables(CacheEntry& ce, hipStream_t s, DevTables* out) {
         }
     Upload u;
     u.device = dev;
-    u.bytes = table_layout(*ce.core).total;
+    const PlanCore& c = *ce.core;
+    const size_t plain = table_layout(c, false).total;
+    const size_t full = table_layout(c, true).total;
+    const bool delay_tables =
+        full - plain <= WF_CACHE_DELAY_TABLE_MAX && full <= WF_CACHE_DEVICE_BUDGET;
+    u.bytes = delay_tables ? full : plain;
+    // room within the budget: evict other entries, least recently used first
+    GeometryCache& gc = cache();
+    while (gc.device_bytes + u.bytes > WF_CACHE_DEVICE_BUDGET) {
+        auto victim = gc.lru.end();
+        for (auto it = gc.lru.begin(); it != gc.lru.end(); ++it)
+            if (&it->second != &ce && !it->second.uploads.empty()) victim = it;
+        if (victim == gc.lru.end()) break;
+        e = free_uploads(victim->second);
+        if (e != hipSuccess) return hip_fail(e, "freeing an evicted geometry table");
+    }
     e = hipMalloc(&u.mem, u.bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(geometry table)");
-    wf_status st = upload_tables(*ce.core, u.mem, s, &u.t);
+    wf_status st = upload_tables(c, u.mem, delay_tables, acq, grid, s, &u.t);
     if (st == WF_OK) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "geometry table upload");
@@ -891,7 +954,7 @@ wf_status resolve(int mode, const wf_probe* probe, const wf_acq* acq, const int3
     CacheEntry* ce = nullptr;
     wf_status st = cached_core(mode, probe, acq, tx_elem, angles, tref, grid, &ce);
     if (st != WF_OK) return st;
-    if ((st = cached_tables(*ce, s, &r->t)) != WF_OK) return st;
+    if ((st = cached_tables(*ce, acq, grid, s, &r->t)) != WF_OK) return st;
     r->core = ce->core;
     return WF_OK;
 }
@@ -946,6 +1009,8 @@ void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const w
     a->neg_inv_c = (float)(-1.0 / acq->c);
     a->tx_tab = t.tx;
     a->ch_tab = t.ch;
+    a->rx_tab = t.rx_q;
+    a->tx_tabq = t.tx_q;
 }
 
 // Checks of the buffers of a DAS-shaped call (after check_geometry).
@@ -1101,7 +1166,7 @@ wf_status das_scratch(int32_t mode, const void* rf, const wf_probe* probe, const
     if ((st = check_das_buffers(rf, acq, grid, out)) != WF_OK) return st;
     std::shared_ptr<const PlanCore> core;
     if ((st = host_plan(mode, probe, acq, tx, ang, tref, grid, &core)) != WF_OK) return st;
-    const size_t tables = table_layout(*core).total;
+    const size_t tables = table_layout(*core, false).total;
     if (tables > scratch_bytes)
         return fail(WF_ERR_UNSUPPORTED,
                     "the geometry tables take %llu bytes, more than the %llu-byte static scratch",
@@ -1111,7 +1176,7 @@ wf_status das_scratch(int32_t mode, const void* rf, const wf_probe* probe, const
     void* scratch = nullptr;
     if ((st = get_scratch(&scratch)) != WF_OK) return st;
     DevTables t;
-    if ((st = upload_tables(*core, scratch, stream, &t)) != WF_OK) return st;
+    if ((st = upload_tables(*core, scratch, false, acq, grid, stream, &t)) != WF_OK) return st;
     char* ws = static_cast<char*>(scratch) + tables;
     return launch_gather(mode, 0, rf, acq, grid, *core, t, out, ws, scratch_bytes - tables,
                          stream);
@@ -1277,25 +1342,36 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
 // plans in caller memory
 // ---------------------------------------------------------------------------
 
+static wf_status check_plan_flags(int32_t flags) {
+    if (flags & ~WF_PLAN_DELAY_TABLES)
+        return fail(WF_ERR_INVALID_ARG, "unknown plan flags 0x%x", (unsigned)flags);
+    return WF_OK;
+}
+
 static wf_status plan_bytes_common(int mode, const wf_probe* probe, const wf_acq* acq,
                                    const int32_t* tx_elem, const double* angles, int32_t tref,
-                                   const wf_grid* grid, uint64_t* bytes) {
+                                   const wf_grid* grid, int32_t flags, uint64_t* bytes) {
     if (!bytes) return fail(WF_ERR_INVALID_ARG, "bytes is NULL");
-    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    wf_status st = check_plan_flags(flags);
+    if (st != WF_OK) return st;
+    st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
     PlanCore c;
     if ((st = make_core(mode, probe, acq, tx_elem, angles, tref, grid, &c)) != WF_OK) return st;
-    *bytes = table_layout(c).total;
+    *bytes = table_layout(c, (flags & WF_PLAN_DELAY_TABLES) != 0).total;
     return ok();
 }
 
 static wf_status plan_build_common(int mode, const wf_probe* probe, const wf_acq* acq,
                                    const int32_t* tx_elem, const double* angles, int32_t tref,
-                                   const wf_grid* grid, void* dev_mem, uint64_t bytes,
-                                   wf_plan** out, void* stream) {
+                                   const wf_grid* grid, int32_t flags, void* dev_mem,
+                                   uint64_t bytes, wf_plan** out, void* stream) {
     if (!out) return fail(WF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    wf_status st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
+    wf_status st = check_plan_flags(flags);
+    if (st != WF_OK) return st;
+    const bool delay_tables = (flags & WF_PLAN_DELAY_TABLES) != 0;
+    st = check_geometry(mode, probe, acq, tx_elem, angles, tref, grid, true);
     if (st != WF_OK) return st;
     if (!dev_mem) return fail(WF_ERR_INVALID_ARG, "dev_mem is NULL");
     if (((uintptr_t)dev_mem & (kTableAlign - 1)) != 0)
@@ -1303,7 +1379,7 @@ static wf_status plan_build_common(int mode, const wf_probe* probe, const wf_acq
     auto c = std::make_shared<PlanCore>();
     if ((st = make_core(mode, probe, acq, tx_elem, angles, tref, grid, c.get())) != WF_OK)
         return st;
-    const size_t need = table_layout(*c).total;
+    const size_t need = table_layout(*c, delay_tables).total;
     if (bytes < need)
         return fail(WF_ERR_WORKSPACE, "plan memory of %llu bytes, %llu needed",
                     (unsigned long long)bytes, (unsigned long long)need);
@@ -1312,7 +1388,9 @@ static wf_status plan_build_common(int mode, const wf_probe* probe, const wf_acq
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if ((st = prepare_kernels(*c, acq, grid)) != WF_OK) return st;
     DevTables t;
-    if ((st = upload_tables(*c, dev_mem, (hipStream_t)stream, &t)) != WF_OK) return st;
+    if ((st = upload_tables(*c, dev_mem, delay_tables, acq, grid, (hipStream_t)stream, &t)) !=
+        WF_OK)
+        return st;
     wf_plan* p = new (std::nothrow) wf_plan;
     if (!p) return fail(WF_ERR_DEVICE, "out of host memory for the plan handle");
     p->magic = kPlanMagic;
@@ -1324,27 +1402,27 @@ static wf_status plan_build_common(int mode, const wf_probe* probe, const wf_acq
 }
 
 wf_status wf_plan_bytes_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
-                             const wf_grid* grid, uint64_t* bytes) {
-    return plan_bytes_common(0, probe, acq, tx_elem, nullptr, 0, grid, bytes);
+                             const wf_grid* grid, int32_t flags, uint64_t* bytes) {
+    return plan_bytes_common(0, probe, acq, tx_elem, nullptr, 0, grid, flags, bytes);
 }
 
 wf_status wf_plan_bytes_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
-                            int32_t tref, const wf_grid* grid, uint64_t* bytes) {
-    return plan_bytes_common(1, probe, acq, nullptr, angles_rad, tref, grid, bytes);
+                            int32_t tref, const wf_grid* grid, int32_t flags, uint64_t* bytes) {
+    return plan_bytes_common(1, probe, acq, nullptr, angles_rad, tref, grid, flags, bytes);
 }
 
 wf_status wf_plan_build_stai(const wf_probe* probe, const wf_acq* acq, const int32_t* tx_elem,
-                             const wf_grid* grid, void* dev_mem, uint64_t bytes, wf_plan** out,
-                             void* stream) {
-    return plan_build_common(0, probe, acq, tx_elem, nullptr, 0, grid, dev_mem, bytes, out,
-                             stream);
+                             const wf_grid* grid, int32_t flags, void* dev_mem, uint64_t bytes,
+                             wf_plan** out, void* stream) {
+    return plan_build_common(0, probe, acq, tx_elem, nullptr, 0, grid, flags, dev_mem, bytes,
+                             out, stream);
 }
 
 wf_status wf_plan_build_pwi(const wf_probe* probe, const wf_acq* acq, const double* angles_rad,
-                            int32_t tref, const wf_grid* grid, void* dev_mem, uint64_t bytes,
-                            wf_plan** out, void* stream) {
-    return plan_build_common(1, probe, acq, nullptr, angles_rad, tref, grid, dev_mem, bytes, out,
-                             stream);
+                            int32_t tref, const wf_grid* grid, int32_t flags, void* dev_mem,
+                            uint64_t bytes, wf_plan** out, void* stream) {
+    return plan_build_common(1, probe, acq, nullptr, angles_rad, tref, grid, flags, dev_mem,
+                             bytes, out, stream);
 }
 
 void wf_plan_destroy(wf_plan* plan) {
@@ -1433,12 +1511,12 @@ wf_status wf_delays(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     // is freed once the stream has run the kernel
     PlanCore c;
     build_geometry(mode, probe, acq, tx_elem, angles_rad, tref, grid, &c.g);
-    const TableLayout L = table_layout(c);
+    const TableLayout L = table_layout(c, false);
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, L.total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(delay tables)");
     DevTables t;
-    st = upload_tables(c, mem, (hipStream_t)stream, &t);
+    st = upload_tables(c, mem, false, acq, grid, (hipStream_t)stream, &t);
     if (st != WF_OK) {
         (void)hipFree(mem);
         return st;

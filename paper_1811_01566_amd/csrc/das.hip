@@ -208,8 +208,18 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // global -> registers for pass t (nothing written yet); a group
         // outside the record reads zeros through the buffer range check
         RawGroup<RT> raw[PP][NG];
+        // STAI transmit delays from the plan's table: loaded with the RF of
+        // their pass (txr), copied aside when it is committed (txc)
+        constexpr bool kTxTab = MODE == 0 && FG == 1;
+        const bool tx_tab = kTxTab && a.tx_tabq != nullptr;
+        uint32_t txr[PP][PX], txc[PP][PX];
         auto issue = [&](int t, int g, int h) {  // pass t of frame frame0 + g into raw[h]
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+            if (kTxTab && tx_tab) {
+                const uint32_t* src = a.tx_tabq + ((size_t)tile * a.T + t) * (NT * PX) + tid;
+#pragma unroll
+                for (int k = 0; k < PX; ++k) txr[h][k] = src[k * NT];
+            }
             // a ragged last group repeats its last frame (results not written)
             const size_t fo = FG == 1 ? 0 : (size_t)min(g, fgc - 1) * frame_elems;
             const __amdgpu_buffer_rsrc_t rsrc =
@@ -229,6 +239,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // the last pair of the record (n = S - 1, no successor) is dropped.
         auto commit = [&](int t, int buf, int h) {  // raw[h] holds pass t
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+            if (kTxTab && tx_tab) {
+#pragma unroll
+                for (int k = 0; k < PX; ++k) txc[h][k] = txr[h][k];
+            }
 #pragma unroll
             for (int gi = 0; gi < NG; ++gi) {
                 const int w = tid + gi * NT;
@@ -269,7 +283,24 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         if (PP == 2 && FG == 1 && t1 < te) issue(t1, 0, PP - 1);
         if (PP == 2 && FG > 1) issue(t, 1, PP - 1);  // second frame of a pair
         uint32_t rq[PX][kChunk];
-        rx_delays<PX>(a, p, c0, bj, rq);
+        if (a.rx_tab) {
+            // the plan's words for (tile, chunk): 16 per pixel slot, 64 bytes
+            const uint4* src = reinterpret_cast<const uint4*>(
+                a.rx_tab + (((size_t)tile * ((a.C + kChunk - 1) / kChunk) + c0 / kChunk) *
+                                (NT * PX) + tid) * kChunk);
+#pragma unroll
+            for (int k = 0; k < PX; ++k)
+#pragma unroll
+                for (int q = 0; q < kChunk / 4; ++q) {
+                    const uint4 v = src[(size_t)k * NT * (kChunk / 4) + q];
+                    rq[k][4 * q] = v.x;
+                    rq[k][4 * q + 1] = v.y;
+                    rq[k][4 * q + 2] = v.z;
+                    rq[k][4 * q + 3] = v.w;
+                }
+        } else {
+            rx_delays<PX>(a, p, c0, bj, rq);
+        }
         int cur = 0;
         // two transmits per barrier: commit (t, t1) into buffers 2 cur and
         // 2 cur + 1 (last read in the pair before the previous barrier),
@@ -289,7 +320,12 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                     if (th < te) {
                         const int at = __builtin_amdgcn_readfirstlane(m_tab[th].x);
                         uint32_t tq[PX];
-                        tx_delays<MODE, PX>(a, p, m_tab[th], q_tab[th], at, tq);
+                        if (kTxTab && tx_tab) {
+#pragma unroll
+                            for (int k = 0; k < PX; ++k) tq[k] = txc[h][k];
+                        } else {
+                            tx_delays<MODE, PX>(a, p, m_tab[th], q_tab[th], at, tq);
+                        }
                         WF_GATHER_PASS(acc[0], lds0 + (uint32_t)(2 * cur + h) * buf_bytes, at);
                     }
                 }
@@ -321,7 +357,12 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                     else if (tn < te) issue(tn, h, h);
                 }
                 const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
-                if (FG == 1) tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+                if (kTxTab && tx_tab) {
+#pragma unroll
+                    for (int k = 0; k < PX; ++k) tq[k] = txc[0][k];
+                } else if (FG == 1) {
+                    tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+                }
 #pragma unroll
                 for (int h = 0; h < PP; ++h) {
                     // 1024-thread workgroups have no registers to keep the sums
@@ -393,6 +434,58 @@ __global__ void __launch_bounds__(256) delays_kernel(const DelayArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Delay tables of a plan: the words the gathers would form, written once
+// ---------------------------------------------------------------------------
+// Workgroup (tile, y) of NT threads, the gather's tile shape: y < chunks
+// writes the receive delays of chunk y, y == chunks (STAI, tx != null) the
+// transmit delays of every transmit.  The tile geometry, pixel set, window
+// bases and delay functions are the gather's own, so each word equals the
+// one the gather forms for the same tile, chunk, transmit and lane.
+template <int MODE, int NT, int PX>
+__global__ void __launch_bounds__(NT) delay_table_kernel(const DasArgs a, uint32_t* __restrict__ rx,
+                                                         uint32_t* __restrict__ tx) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int* b_tab = reinterpret_cast<int*>(smem);                      // 2 kChunk ints
+    int4* m_tab = reinterpret_cast<int4*>(smem + 2 * kChunk * 4);  // T entries
+    float4* q_tab = reinterpret_cast<float4*>(smem + 2 * kChunk * 4 + (size_t)a.T * 16);
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int nch = (a.C + kChunk - 1) / kChunk;
+    const TileGeom g = tile_geom<NT, PX>(a, tile);
+    PixelSet<PX> p;
+    pixel_set<NT, PX>(a, g, p);
+    if ((int)blockIdx.y < nch) {
+        const int c0 = (int)blockIdx.y * kChunk;
+        chunk_tables(a, g, c0, b_tab);
+        __syncthreads();
+        int bj[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) bj[j] = __builtin_amdgcn_readfirstlane(b_tab[j]);
+        uint32_t rq[PX][kChunk];
+        rx_delays<PX>(a, p, c0, bj, rq);
+        uint4* dst = reinterpret_cast<uint4*>(
+            rx + (((size_t)tile * nch + blockIdx.y) * (NT * PX) + tid) * kChunk);
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+#pragma unroll
+            for (int q = 0; q < kChunk / 4; ++q)
+                dst[(size_t)k * NT * (kChunk / 4) + q] =
+                    make_uint4(rq[k][4 * q], rq[k][4 * q + 1], rq[k][4 * q + 2], rq[k][4 * q + 3]);
+    } else if (MODE == 0 && tx) {
+        tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
+        __syncthreads();
+        for (int t = 0; t < a.T; ++t) {
+            const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
+            uint32_t tq[PX];
+            tx_delays<MODE, PX>(a, p, m_tab[t], q_tab[t], at, tq);
+            uint32_t* dst = tx + ((size_t)tile * a.T + t) * (NT * PX) + tid;
+#pragma unroll
+            for (int k = 0; k < PX; ++k) dst[k * NT] = tq[k];
+        }
+    }
+}
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
     return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), lds);
@@ -419,28 +512,32 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
 // 1024-thread tiles runs two passes per barrier (transmits of a single
 // frame, frames of a batch) where the host gave the LDS for it; FP32 RF
 // holds too many staging registers for two passes.
-template <int MODE, typename RT, int NT, int OP>
+template <int MODE, typename RT, int NT, int PX, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
     constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
+    // staged groups per lane: a pass stages at most 16 x 64 groups (nst <= 512)
+    constexpr int NG = (NT == 1024 && PX == 1) ? 1 : 2;
     if constexpr (OP == kOpValue) {
         if (a.F > 1) {
             if constexpr (kPairs)
-                if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 4, 2>(a, lds, s);
-            return launch_one<MODE, RT, NT, 2, 2, OP, 4>(a, lds, s);
+                if (a.pp == 2) return launch_one<MODE, RT, NT, PX, NG, OP, 4, 2>(a, lds, s);
+            return launch_one<MODE, RT, NT, PX, NG, OP, 4>(a, lds, s);
         }
     }
     if constexpr (kPairs)
-        if (a.pp == 2) return launch_one<MODE, RT, NT, 2, 2, OP, 1, 2>(a, lds, s);
-    return launch_one<MODE, RT, NT, 2, 2, OP, 1>(a, lds, s);
+        if (a.pp == 2) return launch_one<MODE, RT, NT, PX, NG, OP, 1, 2>(a, lds, s);
+    return launch_one<MODE, RT, NT, PX, NG, OP, 1>(a, lds, s);
 }
 
-// (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 512 x 2
-// (8 waves), 256 x 4 (4 waves, the same tile as 512 x 2) or 256 x 1 (small
-// tiles for coarse grids)
+// (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 1024 x 1
+// (16 waves on the tile of 512 x 2), 512 x 2 (8 waves), 256 x 4 (4 waves,
+// the same tile again) or 256 x 1 (small tiles for coarse grids)
 template <int MODE, typename RT, int OP>
 hipError_t launch_px(int nt, int px, int groups, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024) return launch_large<MODE, RT, 1024, OP>(a, lds, s);
-    if (nt == 512) return launch_large<MODE, RT, 512, OP>(a, lds, s);
+    if (nt == 1024)
+        return px == 1 ? launch_large<MODE, RT, 1024, 1, OP>(a, lds, s)
+                       : launch_large<MODE, RT, 1024, 2, OP>(a, lds, s);
+    if (nt == 512) return launch_large<MODE, RT, 512, 2, OP>(a, lds, s);
     if (px == 4)
         return groups <= 2 ? launch_one<MODE, RT, 256, 4, 2, OP>(a, lds, s)
                            : launch_one<MODE, RT, 256, 4, 4, OP>(a, lds, s);
@@ -514,7 +611,8 @@ hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s)
 }
 
 static bool shape_ok(int nt, int px, int groups) {
-    if (nt == 1024 || nt == 512) return px == 2 && groups <= 2;
+    if (nt == 1024) return (px == 2 && groups <= 2) || (px == 1 && groups <= 1);
+    if (nt == 512) return px == 2 && groups <= 2;
     return nt == 256 && (px == 4 || px == 1) && groups <= kMaxGroups;
 }
 
@@ -539,6 +637,36 @@ hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, cons
     if (!shape_ok(nt, px, groups)) return hipErrorInvalidValue;
     return mode == 1 ? launch_mode<1, kOpDydc>(dtype, nt, px, groups, a, lds_bytes, s)
                      : launch_mode<0, kOpDydc>(dtype, nt, px, groups, a, lds_bytes, s);
+}
+
+template <int MODE, int NT, int PX>
+hipError_t launch_tables(const DasArgs& a, uint32_t* rx, uint32_t* tx, hipStream_t s) {
+    const size_t lds = 2 * kChunk * 4 + (size_t)a.T * 32;
+    hipError_t e = allow_lds(delay_table_kernel<MODE, NT, PX>, lds);
+    if (e != hipSuccess) return e;
+    const int nch = (a.C + kChunk - 1) / kChunk;
+    const dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)(nch + (MODE == 0 && tx ? 1 : 0)));
+    hipLaunchKernelGGL((delay_table_kernel<MODE, NT, PX>), grid, dim3(NT), lds, s, a, rx, tx);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_tables_shape(int nt, int px, const DasArgs& a, uint32_t* rx, uint32_t* tx,
+                               hipStream_t s) {
+    if (nt == 1024) return px == 1 ? launch_tables<MODE, 1024, 1>(a, rx, tx, s)
+                                   : launch_tables<MODE, 1024, 2>(a, rx, tx, s);
+    if (nt == 512) return launch_tables<MODE, 512, 2>(a, rx, tx, s);
+    return px == 4 ? launch_tables<MODE, 256, 4>(a, rx, tx, s)
+                   : launch_tables<MODE, 256, 1>(a, rx, tx, s);
+}
+
+hipError_t launch_delay_tables(int mode, int nt, int px, const DasArgs& a, uint32_t* rx,
+                               uint32_t* tx, hipStream_t s) {
+    if (!shape_ok(nt, px, 1) || !rx || (long long)a.ntz * a.ntx > 0x7FFFFFFF ||
+        (size_t)a.T * 32 + 2 * kChunk * 4 > kLdsPerCu)
+        return hipErrorInvalidValue;
+    return mode == 1 ? launch_tables_shape<1>(nt, px, a, rx, nullptr, s)
+                     : launch_tables_shape<0>(nt, px, a, rx, tx, s);
 }
 
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s) {

@@ -90,6 +90,13 @@ struct DasArgs {
     const float* ws_gmax;  // adjoint workspace: largest |g| of each launched frame
     int prepare_only;   // 1: set the launch attributes of the kernel this call would
                         // launch (its dynamic LDS limit) and launch nothing
+    // Delay tables of a plan (null: the gathers form the delays themselves;
+    // both give the same words): window-local Q9.23 receive delays, masked
+    // and clamped as the gather uses them, [tile][chunk][pixel slot][16],
+    // and STAI transmit delays [tile][T][pixel slot]; pixel slot = k NT +
+    // thread for pixel k of a thread.
+    const uint32_t* rx_tab;
+    const uint32_t* tx_tabq;
 };
 
 struct DelayArgs {
@@ -138,6 +145,10 @@ constexpr int kStoreWords = 960;
 hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
+// Writes the delay tables of a plan (DasArgs::rx_tab / tx_tabq layout) for
+// the tile shape (nt, px): rx always, tx for STAI (mode 0) when tx != null.
+hipError_t launch_delay_tables(int mode, int nt, int px, const DasArgs& a, uint32_t* rx,
+                               uint32_t* tx, hipStream_t s);
 hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,
                            hipStream_t s);
 hipError_t launch_log_compress(const float* env, const float* col_max, int F, int nz, int nx,

@@ -2,8 +2,9 @@
 
 Requests of different geometries (array size, transmit count, record length,
 pixel grid, STAI or PWI) arrive over time.  The service keeps, per shape
-class, resident executors: a plan of the geometry (delay tables and work
-list in device memory the executor owns), device buffers for one frame (RF
+class, resident executors: a plan of the geometry (constant tables, work
+list and, where they are small against the memory budget, the delay tables,
+in device memory the executor owns), device buffers for one frame (RF
 in, beamformed RF, B-mode out, column maxima, the DAS work-split workspace)
 and a HIP graph of the whole path (DAS -> envelope -> log compression),
 captured on the executor's first call and replayed per request.  Up to ``n_streams`` requests are in
@@ -85,13 +86,13 @@ class Executor:
     one shape class.  The plan's device tables live as long as the executor
     and its graph."""
 
-    def __init__(self, req: Request, device, use_graph: bool):
+    def __init__(self, req: Request, device, use_graph: bool, delay_tables: bool = False):
         import torch
 
         g = req.scan.grid
         self.scan = req.scan
         self.dr_db = req.dr_db
-        self.plan = Plan(req.scan, req.n_s, device=device)
+        self.plan = Plan(req.scan, req.n_s, device=device, delay_tables=delay_tables)
         self.rf = torch.zeros((1, req.scan.n_tx, req.scan.n_ch, req.n_s), dtype=torch.int16,
                               device=device)
         self.y = torch.empty((1, g.nz, g.nx), dtype=torch.float32, device=device)
@@ -124,7 +125,10 @@ class Executor:
 
 
 class GpuBackend:
-    """Streams, events and executors on one GPU."""
+    """Streams, events and executors on one GPU.  An executor's plan holds
+    the delay tables (see :class:`Plan`) when they take at most
+    ``table_limit`` bytes; the :class:`Server` sets it to a sixteenth of its
+    HBM budget."""
 
     def __init__(self, device="cuda:0", use_graphs: bool = True):
         import torch
@@ -132,16 +136,21 @@ class GpuBackend:
         self.torch = torch
         self.device = torch.device(device)
         self.use_graphs = use_graphs
+        self.table_limit = 0
 
     def new_stream(self):
         return self.torch.cuda.Stream(device=self.device)
 
+    def _delay_tables(self, req: Request) -> bool:
+        extra = plan_bytes(req.scan, req.n_s, True) - plan_bytes(req.scan, req.n_s, False)
+        return extra <= self.table_limit
+
     def new_executor(self, req: Request) -> Executor:
-        return Executor(req, self.device, self.use_graphs)
+        return Executor(req, self.device, self.use_graphs, self._delay_tables(req))
 
     def executor_bytes(self, req: Request) -> int:
         return (frame_bytes(req) + das_workspace_bytes(req.scan, req.n_s, 1) +
-                plan_bytes(req.scan, req.n_s))
+                plan_bytes(req.scan, req.n_s, self._delay_tables(req)))
 
     def launch(self, ex: Executor, req: Request, stream):
         torch = self.torch
@@ -174,6 +183,8 @@ class Server:
     def __init__(self, backend=None, hbm_budget: int = 8 << 30, n_streams: int = 4):
         self.backend = backend if backend is not None else GpuBackend()
         self.budget = int(hbm_budget)
+        if hasattr(self.backend, "table_limit"):
+            self.backend.table_limit = self.budget // 16
         self.streams = [self.backend.new_stream() for _ in range(n_streams)]
         self.free_slots = list(range(n_streams))
         self.executors: Dict[tuple, List[object]] = collections.defaultdict(list)

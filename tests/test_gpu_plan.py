@@ -55,6 +55,69 @@ def test_plan_equals_no_plan(wf_gpu, name):
     assert nl2(a[0].cpu().numpy(), ref) <= 1e-5
 
 
+def _table_cases():
+    """Geometries over every tile shape and delay path: STAI small (256 x 1
+    tiles, split, work list), STAI with t0 != 0 and an f-number (transmit
+    delays with a time origin, apodised receive words), a STAI sub-grid on
+    1024 x 1 tiles, PWI sub-grid (1024 x 2 tiles, two passes per barrier),
+    PWI deeper than its record, and the full 1024 x 512 PWI frame (1024 x 2
+    tiles; its oracle parity is the full-frame test's)."""
+    from wfhelp import deep_pwi
+
+    full = lighter(phantom.get_workload("stai_full"), 2000)
+    return {
+        "stai_small": phantom.get_workload("stai_small"),
+        # (no pixel lies within 1e-4 of an aperture edge: at an exact tie
+        # 2 F# |x - x_j| = z, float rounding decides either way)
+        "stai_t0_fnum": phantom.tiny_stai(n_elem=32, n_tx=32, n_ch=32, n_s=1024, nz=96, nx=40,
+                                          z_min=4.05e-3, z_max=11.9e-3, f_number=1.17,
+                                          t0=0.35e-6),
+        "stai_full_sub": subgrid(full.with_(n_tx=48), 64, 192, 40, 96),
+        "pwi_sub": subgrid(lighter(phantom.get_workload("pwi")), 300, 128, 200, 96),
+        "deep_pwi": deep_pwi(),
+        "pwi_full": lighter(phantom.get_workload("pwi")),
+    }
+
+
+@pytest.mark.parametrize("name", ["stai_small", "stai_t0_fnum", "stai_full_sub", "pwi_sub",
+                                  "deep_pwi", "pwi_full"])
+def test_delay_tables_give_the_same_bits(wf_gpu, name):
+    """A plan with the delay tables (the gathers read the receive and STAI
+    transmit words) and one without (the gathers form them) give the same
+    bits: single frames with and without the split workspace, a batch of
+    three frames (frame groups), FP32 RF and d y / d c; and the oracle's
+    result within 1e-5."""
+    torch = _t()
+    w = _table_cases()[name]
+    scan = scan_from_workload(w)
+    rf_np = phantom.synth_rf(w)
+    rf = torch.from_numpy(rf_np).cuda()
+    with_t = wf_gpu.Plan(scan, w.n_s, delay_tables=True)
+    without = wf_gpu.Plan(scan, w.n_s, delay_tables=False)
+    assert with_t.mem.numel() > without.mem.numel()
+    outs = {}
+    for key, plan in (("tables", with_t), ("plain", without)):
+        wsb = plan.workspace_bytes(3)[0]
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda") if wsb else None
+        rf3 = rf.repeat(3, 1, 1, 1)
+        rf3[1] = torch.roll(rf[0], 7, dims=-1)
+        rf3[2] = -rf[0]
+        outs[key] = (wf_gpu.das(scan, rf, plan=plan, workspace=ws),
+                     wf_gpu.das(scan, rf, plan=plan),
+                     wf_gpu.das(scan, rf3, plan=plan, workspace=ws),
+                     wf_gpu.das(scan, rf.float(), plan=plan),
+                     wf_gpu.das_dydc(scan, rf.float(), plan=plan))
+    torch.cuda.synchronize()
+    for a, b in zip(outs["tables"], outs["plain"]):
+        assert torch.equal(a, b)
+    if name == "pwi_full":
+        return
+    ref = oracle.das_workload(rf_np[0].astype(np.float64), w)
+    err = nl2(outs["tables"][0][0].cpu().numpy(), ref)
+    print(f"{name}: nL2 {err:.2e}")
+    assert err <= 1e-5
+
+
 def test_plan_of_another_geometry_is_refused(wf_gpu):
     torch = _t()
     w = phantom.get_workload("stai_small")

@@ -36,9 +36,9 @@ def _stai(c=1540.0, n=32, n_s=1024):
     return probe, acq, grid
 
 
-def _pwi_bytes(lib, probe, acq, grid, ang):
+def _pwi_bytes(lib, probe, acq, grid, ang, flags=0):
     n = ctypes.c_uint64(0)
-    st = lib.wf_plan_bytes_pwi(probe, acq, ang, 0, grid, ctypes.byref(n))
+    st = lib.wf_plan_bytes_pwi(probe, acq, ang, 0, grid, flags, ctypes.byref(n))
     assert st == 0, lib.wf_last_error()
     return n.value
 
@@ -59,8 +59,49 @@ def test_plan_bytes_hold_the_tables(lib):
     assert b >= tx + ch + 256 and b % 256 == 0
     p, a, g = _stai()
     n = ctypes.c_uint64(0)
-    assert lib.wf_plan_bytes_stai(p, a, None, g, ctypes.byref(n)) == 0
+    assert lib.wf_plan_bytes_stai(p, a, None, g, 0, ctypes.byref(n)) == 0
     assert n.value >= math.ceil(32 * 32 / 256) * 256 + math.ceil(32 * 16 / 256) * 256
+
+
+def _tile_slots(w):
+    """Pixel slots of the launch plan: tiles x threads x pixels per thread."""
+    import paper_1811_01566_amd as wf
+    from wfhelp import scan_from_workload
+
+    info = wf.tile_info(scan_from_workload(w), w.n_s, 1)
+    return info["ntz"] * info["ntx"] * info["threads"] * info["px"]
+
+
+@pytest.mark.parametrize("name", ["stai_small", "pwi"])
+def test_delay_tables_add_one_word_per_slot_and_element(lib, name):
+    """WF_PLAN_DELAY_TABLES adds, 256-byte aligned, 4 bytes per (pixel slot,
+    channel padded to 16) and, for STAI, per (pixel slot, transmit)."""
+    import paper_1811_01566_amd as wf
+    import phantom
+    from wfhelp import scan_from_workload
+
+    w = phantom.get_workload(name)
+    scan = scan_from_workload(w)
+    plain = wf.plan_bytes(scan, w.n_s, delay_tables=False)
+    full = wf.plan_bytes(scan, w.n_s, delay_tables=True)
+    slots = _tile_slots(w)
+    rx = slots * math.ceil(w.n_ch / 16) * 16 * 4
+    tx = slots * w.n_tx * 4 if w.mode == "stai" else 0
+    align = lambda v: math.ceil(v / 256) * 256  # noqa: E731
+    assert full - plain == align(rx) + align(tx)
+    if name == "pwi":  # 1024 x 512 grid, 128 channels: 256 MiB of receive words
+        assert full - plain == 256 << 20
+
+
+def test_unknown_plan_flags_are_refused(lib):
+    probe, acq, grid, ang = _pwi()
+    n = ctypes.c_uint64(0)
+    assert lib.wf_plan_bytes_pwi(probe, acq, ang, 0, grid, 2, ctypes.byref(n)) == -1
+    assert "flags" in lib.wf_last_error().decode()
+    out = ctypes.c_void_p(0x1)
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0x100, FAKE, 1 << 30,
+                                 ctypes.byref(out), None) == -1
+    assert out.value is None
 
 
 def test_hundred_speeds_of_sound_add_nothing_to_the_cache(lib):
@@ -81,26 +122,27 @@ def test_plan_build_checks_before_the_device(lib):
     need = _pwi_bytes(lib, probe, acq, grid, ang)
     out = ctypes.c_void_p(0x1)
     # no out pointer
-    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, FAKE, need, None, None) == -1
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0, FAKE, need, None, None) == -1
     # no device memory
-    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, None, need, ctypes.byref(out),
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0, None, need, ctypes.byref(out),
                                  None) == -1
     assert out.value is None  # cleared on failure
     # misaligned device memory
-    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, ctypes.c_void_p(0x10040), need,
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0, ctypes.c_void_p(0x10040), need,
                                  ctypes.byref(out), None) == -1
     assert "256-byte" in lib.wf_last_error().decode()
     # too small: WF_ERR_WORKSPACE, nothing written
-    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, FAKE, need - 256, ctypes.byref(out),
-                                 None) == -4
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0, FAKE, need - 256,
+                                 ctypes.byref(out), None) == -4
     assert "needed" in lib.wf_last_error().decode()
     # an invalid geometry fails validation first
     acq.c = -1.0
-    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, FAKE, need, ctypes.byref(out),
+    assert lib.wf_plan_build_pwi(probe, acq, ang, 0, grid, 0, FAKE, need, ctypes.byref(out),
                                  None) == -1
     p, a, g = _stai()
     a.n_tx = 0
-    assert lib.wf_plan_build_stai(p, a, None, g, FAKE, 1 << 20, ctypes.byref(out), None) == -1
+    assert lib.wf_plan_build_stai(p, a, None, g, 0, FAKE, 1 << 20, ctypes.byref(out),
+                                  None) == -1
 
 
 def test_plan_destroy_and_queries_tolerate_null(lib):
@@ -117,7 +159,10 @@ def test_binding_plan_bytes_match_the_library():
                    grid=wf.Grid(256, 128, 5e-3, 25e-3 / 255, -9.45e-3, 18.9e-3 / 127),
                    angles_rad=tuple(np.radians(np.linspace(-16, 16, 16))))
     probe, acq, grid, ang = _pwi()
-    assert wf.plan_bytes(scan, 2048) == _pwi_bytes(_lib.load(), probe, acq, grid, ang)
+    assert wf.plan_bytes(scan, 2048, delay_tables=False) == _pwi_bytes(_lib.load(), probe, acq,
+                                                                       grid, ang)
+    assert wf.plan_bytes(scan, 2048) == _pwi_bytes(_lib.load(), probe, acq, grid, ang,
+                                                   _lib.WF_PLAN_DELAY_TABLES)
 
 
 def test_binding_refuses_lists_shorter_than_the_geometry():

@@ -39,6 +39,8 @@ PEAK_FMA = 2 * PEAK_LANE_OPS
 # algorithmic lane-ops of one active contribution: transmit + receive delay
 # add, index / fraction split, r[n+1] - r[n], interpolating FMA, accumulate
 OPS_PER_CONTRIB = 5
+# shape classes of the short served-stream summary on the single-workload line
+SUMMARY_CLASSES = 8
 
 PAPER_CONTEXT = {
     "source": "WaveFlow (arXiv 1811.01566) Table I, NVIDIA Titan X, TF 1.6, float64 input",
@@ -74,6 +76,9 @@ def parse():
     ap.add_argument("--serve-classes", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.75,
                     help="arrival rate as a fraction of the plain path's capacity")
+    ap.add_argument("--serve-summary", type=int, default=300, metavar="REQUESTS",
+                    help="requests of the short served-stream summary added to the "
+                         "single-workload line (8 shape classes; 0 leaves it out)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (reference "
                          "for the HBM byte counters), and exit")
@@ -230,16 +235,19 @@ def cpu_baseline(w, rf, ncols, pool_columns):
     }
 
 
-def serve_main(args, wf, phantom, torch, np):
-    """Served mixed stream: Poisson arrivals over a pool of shape classes at a
-    fixed fraction of the plain path's capacity; both paths replay the same
-    trace and report per-request latency (arrival -> completion)."""
+def served_stream(wf, phantom, torch, np, n_classes, n_requests, load, n_warm, n_burst,
+                  n_check):
+    """Served mixed stream: Poisson arrivals over a seeded pool of shape
+    classes (speckle + cyst phantoms) at `load` x the plain path's capacity;
+    the server (continuous batching, graphs, 4 streams) and the plain
+    per-frame path replay the same trace and report per-request latency
+    (arrival -> completion).  Returns the summary."""
     from phantom.configs import served_pool
 
     from paper_1811_01566_amd.serve import (GpuBackend, Request, Server, latency_stats,
                                             poisson_trace, run_plain)
 
-    pool = served_pool(args.serve_classes)
+    pool = served_pool(n_classes)
     dev = torch.device("cuda:0")
     rfs = [torch.from_numpy(phantom.synth_rf(w)[0]).to(dev) for w in pool]
     scans = [scan_of(wf, w) for w in pool]
@@ -255,37 +263,31 @@ def serve_main(args, wf, phantom, torch, np):
             torch.cuda.synchronize()
         svc.append((time.perf_counter() - t) / 10)
     capacity = 1.0 / float(np.mean(svc))
-    rate = args.serve_load * capacity
-    arrivals, cls = poisson_trace(pool, rate, args.serve_requests, seed=5)
+    rate = load * capacity
+    arrivals, cls = poisson_trace(pool, rate, n_requests, seed=5)
     reqs = [Request(i, scans[k], rfs[k], float(t), pool[k].dr_db)
             for i, (t, k) in enumerate(zip(arrivals, cls))]
     print(f"[bench] serve: {len(pool)} classes, plain capacity {capacity:.0f} frames/s, "
-          f"arrival rate {rate:.0f}/s", file=sys.stderr, flush=True)
+          f"arrival rate {rate:.0f}/s, {len(reqs)} requests", file=sys.stderr, flush=True)
     budget = 16 << 30
     srv = Server(GpuBackend("cuda:0", use_graphs=True), hbm_budget=budget, n_streams=4)
     srv.prewarm(reqs)  # executors (buffers + captured graphs) for every class
-    srv.run_trace(reqs[: min(200, len(reqs))])  # warm-up
+    srv.run_trace(reqs[: min(n_warm, len(reqs))])  # warm-up
     srv.results.clear()
     built_before = srv.executors_built
     served = latency_stats(srv.run_trace(reqs))
     built_during = srv.executors_built - built_before
     plain = latency_stats(run_plain(reqs))
     ok = all(torch.equal(a.image, b.image) for a, b in
-             zip(srv.run_trace(reqs[:64]), run_plain(reqs[:64])))
+             zip(srv.run_trace(reqs[:n_check]), run_plain(reqs[:n_check])))
     # saturation: the same requests all arriving at once
-    burst = [Request(r.rid, r.scan, r.rf, 0.0, r.dr_db) for r in reqs[: min(600, len(reqs))]]
+    burst = [Request(r.rid, r.scan, r.rf, 0.0, r.dr_db) for r in reqs[: min(n_burst, len(reqs))]]
     served_sat = latency_stats(srv.run_trace(burst))["throughput_rps"]
     plain_sat = latency_stats(run_plain(burst))["throughput_rps"]
-    res = {
-        "metric": "B-mode frames/s + DAS Gsamples/s (PWI 128ch×64tx); p99 frame latency",
-        "value": round(served["throughput_rps"], 2), "unit": "frames/s",
-        "n_gpus": 1, "steps": len(reqs), "warmup": 200,
-        "ms_per_step": round(1e3 / served["throughput_rps"], 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "served_mixed_stream", "classes": [w.name for w in pool],
-                   "arrival": f"Poisson, {args.serve_load:.2f} x plain capacity",
-                   "streams": 4, "hbm_budget_bytes": budget, "graphs": True},
+    return {
+        "classes": [w.name for w in pool], "requests": len(reqs),
+        "arrival": f"Poisson, {load:.2f} x plain capacity",
+        "streams": 4, "hbm_budget_bytes": budget, "graphs": True,
         "served": served, "plain": plain,
         "plain_capacity_fps": capacity, "arrival_rate_hz": rate,
         "saturation_fps": {"served": round(served_sat, 2), "plain": round(plain_sat, 2),
@@ -294,6 +296,26 @@ def serve_main(args, wf, phantom, torch, np):
         "executors_built": srv.executors_built,
         "executors_built_during_trace": built_during, "max_in_flight": srv.max_inflight,
     }
+
+
+def serve_main(args, wf, phantom, torch, np):
+    """The served mixed stream as the headline of its own JSON line."""
+    s = served_stream(wf, phantom, torch, np, args.serve_classes, args.serve_requests,
+                      args.serve_load, 200, 600, 64)
+    served = s["served"]
+    res = {
+        "metric": "B-mode frames/s + DAS Gsamples/s (PWI 128ch×64tx); p99 frame latency",
+        "value": round(served["throughput_rps"], 2), "unit": "frames/s",
+        "n_gpus": 1, "steps": s["requests"], "warmup": 200,
+        "ms_per_step": round(1e3 / served["throughput_rps"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served_mixed_stream", "classes": s["classes"],
+                   "arrival": s["arrival"], "streams": s["streams"],
+                   "hbm_budget_bytes": s["hbm_budget_bytes"], "graphs": True},
+    }
+    res.update({k: v for k, v in s.items()
+                if k not in ("classes", "arrival", "streams", "hbm_budget_bytes", "graphs")})
     print(json.dumps(res), flush=True)
 
 
@@ -391,6 +413,11 @@ def main():
 
     w = phantom.get_workload(args.workload)
     # synthesise before the GPU is initialised (the generator forks workers)
+    if args.serve_summary:
+        from phantom.configs import served_pool
+
+        for w0 in served_pool(SUMMARY_CLASSES):
+            phantom.synth_rf(w0)
     print(f"[bench] synthesising {w.name} RF ...", file=sys.stderr, flush=True)
     t_syn = time.perf_counter()
     rf_np = phantom.synth_rf(w)
@@ -536,6 +563,12 @@ def main():
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.asarray(lat)
 
+    # ---- short served mixed stream beside the headline (p50 / p99) ----------
+    serve_summary = None
+    if args.serve_summary:
+        serve_summary = served_stream(wf, phantom, torch, np, SUMMARY_CLASSES,
+                                      args.serve_summary, 0.75, 50, 200, 16)
+
     fps = F * args.steps / wall
     das_avg_s = float(np.mean(das_ms)) * 1e-3
     nominal = w.nominal_contributions
@@ -591,6 +624,8 @@ def main():
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
+    if serve_summary is not None:
+        res["served_stream"] = serve_summary
     print(json.dumps(res), flush=True)
 
 

@@ -134,7 +134,35 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const int tile = item / a.nsplit;
     const int split = item - tile * a.nsplit;
     const TileGeom g = tile_geom<NT, PX>(a, tile);
+    // split: this workgroup sums channel chunks [cb, ce) x transmits [tb, te)
+    const int ssc = split / a.nts;
+    const int cb = ssc * a.split_chunks * kChunk;
+    const int ce = min(a.C, cb + a.split_chunks * kChunk);
+    const int tb = (split - ssc * a.nts) * a.split_tx;
+    const int te = min(a.T, tb + a.split_tx);
+    // receive words of a chunk from the plan's delay table: 16 per pixel
+    // slot, 64 bytes (the first chunk's go out before any table is built)
+    uint32_t rq[PX][kChunk];
+    auto load_rq = [&](int c0) {
+        const uint4* src = reinterpret_cast<const uint4*>(
+            a.rx_tab + (((size_t)tile * ((a.C + kChunk - 1) / kChunk) + c0 / kChunk) * (NT * PX) +
+                        tid) * kChunk);
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+#pragma unroll
+            for (int q = 0; q < kChunk / 4; ++q) {
+                const uint4 v = src[(size_t)k * NT * (kChunk / 4) + q];
+                rq[k][4 * q] = v.x;
+                rq[k][4 * q + 1] = v.y;
+                rq[k][4 * q + 2] = v.z;
+                rq[k][4 * q + 3] = v.w;
+            }
+    };
+    if (a.rx_tab && cb < ce) load_rq(cb);
+    // per-transmit tables and the first chunk's bases (the last kChunk
+    // threads), published by the first chunk's barrier
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
+    if (cb < ce) chunk_tables(a, g, cb, b_tab, NT - kChunk);
     // zero pad behind every window of every buffer (never overwritten)
     {
         const int pad = slot - a.nst;
@@ -155,15 +183,11 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     const RT* rf_frame = reinterpret_cast<const RT*>(a.rf) + (size_t)frame0 * frame_elems;
     const int ngroups = kChunk * a.ng;  // staged 8-sample groups per pass (<= NG * NT)
 
-    // split: this workgroup sums channel chunks [cb, ce) x transmits [tb, te)
-    const int ssc = split / a.nts;
-    const int cb = ssc * a.split_chunks * kChunk;
-    const int ce = min(a.C, cb + a.split_chunks * kChunk);
-    const int tb = (split - ssc * a.nts) * a.split_tx;
-    const int te = min(a.T, tb + a.split_tx);
     for (int c0 = cb; c0 < ce; c0 += kChunk) {
-        __syncthreads();  // previous chunk's readers of b_tab / windows are done
-        chunk_tables(a, g, c0, b_tab);
+        if (c0 != cb) {
+            __syncthreads();  // previous chunk's readers of b_tab / windows are done
+            chunk_tables(a, g, c0, b_tab);
+        }
         __syncthreads();
         int bj[kChunk];
         int any_act = 0, bmin = 0x7fffffff, bmax = -0x7fffffff;
@@ -282,22 +306,8 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         int t1 = PP == 2 && FG == 1 ? next_active(t + 1) : te;  // second transmit of a pair
         if (PP == 2 && FG == 1 && t1 < te) issue(t1, 0, PP - 1);
         if (PP == 2 && FG > 1) issue(t, 1, PP - 1);  // second frame of a pair
-        uint32_t rq[PX][kChunk];
         if (a.rx_tab) {
-            // the plan's words for (tile, chunk): 16 per pixel slot, 64 bytes
-            const uint4* src = reinterpret_cast<const uint4*>(
-                a.rx_tab + (((size_t)tile * ((a.C + kChunk - 1) / kChunk) + c0 / kChunk) *
-                                (NT * PX) + tid) * kChunk);
-#pragma unroll
-            for (int k = 0; k < PX; ++k)
-#pragma unroll
-                for (int q = 0; q < kChunk / 4; ++q) {
-                    const uint4 v = src[(size_t)k * NT * (kChunk / 4) + q];
-                    rq[k][4 * q] = v.x;
-                    rq[k][4 * q + 1] = v.y;
-                    rq[k][4 * q + 2] = v.z;
-                    rq[k][4 * q + 3] = v.w;
-                }
+            if (c0 != cb) load_rq(c0);
         } else {
             rx_delays<PX>(a, p, c0, bj, rq);
         }

@@ -315,13 +315,15 @@ __device__ __forceinline__ void pixel_set(const DasArgs& a, const TileGeom& g,
     }
 }
 
-// Channel bases of a chunk (threads 0..kChunk-1): b_tab[j] = integer base of
+// Channel bases of a chunk (threads first_thread .. + kChunk - 1): b_tab[j] = integer base of
 // the receive delay over the tile, b_tab[kChunk + j] = 1 if the receive
 // aperture of channel c0 + j reaches the tile (one sample of margin).
 __device__ __forceinline__ void chunk_tables(const DasArgs& a, const TileGeom& g, int c0,
-                                             int* b_tab) {
-    const int tid = threadIdx.x;
-    if (tid < kChunk) {
+                                             int* b_tab, int first_thread = 0) {
+    // this thread's channel of the chunk; threads outside
+    // [first_thread, first_thread + kChunk) have none
+    const int tid = (int)threadIdx.x - first_thread;
+    if (tid >= 0 && tid < kChunk) {
         const int c = c0 + tid;
         int b = 0, act = 0;
         if (c < a.C) {

@@ -364,12 +364,14 @@ wf_status wf_moments(const float* env, int32_t n_frames, int32_t nz, int32_t nx,
  *
  * flags: 0 or WF_PLAN_DELAY_TABLES.  With it the plan also holds the
  * window-local fixed-point delays the gathers use (Sec. II-B: the time of
- * flight of every pixel to every receive element and, for STAI, from every
- * transmit element), formed once on the device at build time: 4 bytes per
- * (pixel slot, channel) plus, for STAI, per (pixel slot, transmit) - about
- * 256 MiB for 128 channels on a 1024 x 512 grid.  The DAS and d y / d c
- * gathers then read those words instead of forming them, with bitwise the
- * same results.  Other flag bits are refused (WF_ERR_INVALID_ARG).
+ * flight of every pixel to every receive element and of every transmit,
+ * from its element (STAI) or its plane wave (PWI)), formed once on the
+ * device at build time: 4 bytes per (pixel slot, channel) and per (pixel
+ * slot, transmit); the transmit words are left out for PWI on the 1024-
+ * thread, 2-pixel tiles, whose gather forms them faster - 256 MiB for 128
+ * channels on a 1024 x 512 PWI grid.  The DAS and d y / d c gathers then
+ * read those words instead of forming them, with bitwise the same results.
+ * Other flag bits are refused (WF_ERR_INVALID_ARG).
  *
  * wf_plan_build_stai / wf_plan_build_pwi: computes the launch plan on the
  * host and writes the device tables into dev_mem (DEVICE, caller-owned,

@@ -211,9 +211,10 @@ class Plan:
     while work that uses it may run (graph replays included).
 
     ``delay_tables`` (default) also stores the gathers' window-local delays
-    of every pixel and element, formed once on the device (about 256 MiB
-    for 128 channels on a 1024 x 512 grid): the DAS and d y / d c calls then
-    skip forming them, with bitwise the same results."""
+    of every pixel to every channel and from every transmit, formed once on
+    the device (256 MiB for 128 channels on a 1024 x 512 PWI grid, whose
+    gather forms its transmit delays itself): the DAS and d y / d c calls
+    then skip forming them, with bitwise the same results."""
 
     def __init__(self, scan: Scan, n_s: int, device=None, stream=None,
                  delay_tables: bool = True):

@@ -640,14 +640,14 @@ wf_status make_core(int mode, const wf_probe* probe, const wf_acq* acq, const in
 
 // Device tables of a plan, inside one block of device memory:
 // [TxConst x T][ChConst x C][int x work-list items] and, in plans built with
-// delay tables, [receive delay words][STAI transmit delay words]; each part
+// delay tables, [receive delay words][transmit delay words]; each part
 // 256-byte aligned.
 struct DevTables {
     const wf::TxConst* tx = nullptr;
     const wf::ChConst* ch = nullptr;
     const int* items = nullptr;       // null when the plan has no work list
     const uint32_t* rx_q = nullptr;   // receive delay table (null: none)
-    const uint32_t* tx_q = nullptr;   // STAI transmit delay table (null: none)
+    const uint32_t* tx_q = nullptr;   // transmit delay table (null: none)
 };
 
 constexpr size_t kTableAlign = 256;
@@ -661,7 +661,7 @@ void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const w
                wf::DasArgs* a);
 
 // Words of the delay tables (DasArgs::rx_tab, tx_tabq): per tile and pixel
-// slot, 16 receive words per channel chunk and, for STAI, one transmit word
+// slot, 16 receive words per channel chunk and one transmit word
 // per transmit.
 size_t rx_table_words(const PlanCore& c) {
     const size_t tiles = (size_t)c.tp.ntz * c.tp.ntx;
@@ -669,7 +669,7 @@ size_t rx_table_words(const PlanCore& c) {
     return tiles * nch * (size_t)c.tp.threads * c.tp.px * wf::kChunk;
 }
 size_t tx_table_words(const PlanCore& c) {
-    if (c.mode != 0) return 0;
+    if (!wf::das_tx_words(c.mode, c.tp.threads, c.tp.px)) return 0;
     return (size_t)c.tp.ntz * c.tp.ntx * c.n_tx * (size_t)c.tp.threads * c.tp.px;
 }
 

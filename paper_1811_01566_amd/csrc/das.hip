@@ -232,9 +232,10 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // global -> registers for pass t (nothing written yet); a group
         // outside the record reads zeros through the buffer range check
         RawGroup<RT> raw[PP][NG];
-        // STAI transmit delays from the plan's table: loaded with the RF of
-        // their pass (txr), copied aside when it is committed (txc)
-        constexpr bool kTxTab = MODE == 0 && FG == 1;
+        // transmit delays from the plan's table: loaded with the RF of their
+        // pass (txr), copied aside when it is committed (txc); the plan
+        // holds them for every shape but PWI on 1024 x 2 tiles
+        constexpr bool kTxTab = FG == 1 && das_tx_words(MODE, NT, PX);
         const bool tx_tab = kTxTab && a.tx_tabq != nullptr;
         uint32_t txr[PP][PX], txc[PP][PX];
         auto issue = [&](int t, int g, int h) {  // pass t of frame frame0 + g into raw[h]
@@ -448,7 +449,7 @@ __global__ void __launch_bounds__(256) delays_kernel(const DelayArgs a) {
 // Delay tables of a plan: the words the gathers would form, written once
 // ---------------------------------------------------------------------------
 // Workgroup (tile, y) of NT threads, the gather's tile shape: y < chunks
-// writes the receive delays of chunk y, y == chunks (STAI, tx != null) the
+// writes the receive delays of chunk y, y == chunks (tx != null) the
 // transmit delays of every transmit.  The tile geometry, pixel set, window
 // bases and delay functions are the gather's own, so each word equals the
 // one the gather forms for the same tile, chunk, transmit and lane.
@@ -482,7 +483,7 @@ __global__ void __launch_bounds__(NT) delay_table_kernel(const DasArgs a, uint32
             for (int q = 0; q < kChunk / 4; ++q)
                 dst[(size_t)k * NT * (kChunk / 4) + q] =
                     make_uint4(rq[k][4 * q], rq[k][4 * q + 1], rq[k][4 * q + 2], rq[k][4 * q + 3]);
-    } else if (MODE == 0 && tx) {
+    } else if (tx) {
         tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
         __syncthreads();
         for (int t = 0; t < a.T; ++t) {
@@ -655,7 +656,7 @@ hipError_t launch_tables(const DasArgs& a, uint32_t* rx, uint32_t* tx, hipStream
     hipError_t e = allow_lds(delay_table_kernel<MODE, NT, PX>, lds);
     if (e != hipSuccess) return e;
     const int nch = (a.C + kChunk - 1) / kChunk;
-    const dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)(nch + (MODE == 0 && tx ? 1 : 0)));
+    const dim3 grid((unsigned)(a.ntz * a.ntx), (unsigned)(nch + (tx ? 1 : 0)));
     hipLaunchKernelGGL((delay_table_kernel<MODE, NT, PX>), grid, dim3(NT), lds, s, a, rx, tx);
     return hipGetLastError();
 }
@@ -675,7 +676,7 @@ hipError_t launch_delay_tables(int mode, int nt, int px, const DasArgs& a, uint3
     if (!shape_ok(nt, px, 1) || !rx || (long long)a.ntz * a.ntx > 0x7FFFFFFF ||
         (size_t)a.T * 32 + 2 * kChunk * 4 > kLdsPerCu)
         return hipErrorInvalidValue;
-    return mode == 1 ? launch_tables_shape<1>(nt, px, a, rx, nullptr, s)
+    return mode == 1 ? launch_tables_shape<1>(nt, px, a, rx, tx, s)
                      : launch_tables_shape<0>(nt, px, a, rx, tx, s);
 }
 

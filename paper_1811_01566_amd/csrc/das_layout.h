@@ -38,6 +38,15 @@ constexpr int das_gather_nbuf(int pp) { return 2 * pp; }
 // Window arrays of an adjoint with nsets window sets (G and H each).
 constexpr int das_adjoint_nbuf(int nsets) { return 2 * nsets; }
 
+// Whether a plan with delay tables holds transmit words for the gathers of
+// this tile shape: every shape but PWI (mode 1) on 1024 x 2 tiles.  That
+// gather sits at its 128-register limit, and loading the words cost it 6 %
+// where forming its (linear) transmit delays costs about 0.3 VALU per
+// contribution (measured on the 1024 x 512 grid).
+constexpr bool das_tx_words(int mode, int nt, int px) {
+    return !(mode == 1 && nt == 1024 && px == 2);
+}
+
 // True when `lds` bytes hold the layout of nbuf arrays for this slot and T.
 constexpr bool das_lds_fits(size_t lds, int nbuf, int slot, int T) {
     return lds >= das_lds(nbuf, slot, T).total;

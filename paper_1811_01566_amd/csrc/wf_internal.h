@@ -93,7 +93,7 @@ struct DasArgs {
     // Delay tables of a plan (null: the gathers form the delays themselves;
     // both give the same words): window-local Q9.23 receive delays, masked
     // and clamped as the gather uses them, [tile][chunk][pixel slot][16],
-    // and STAI transmit delays [tile][T][pixel slot]; pixel slot = k NT +
+    // and transmit delays [tile][T][pixel slot]; pixel slot = k NT +
     // thread for pixel k of a thread.
     const uint32_t* rx_tab;
     const uint32_t* tx_tabq;
@@ -146,7 +146,7 @@ hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s)
 hipError_t launch_dot(const float* a, const float* b, size_t n, float* out, hipStream_t s);
 hipError_t launch_delays(int mode, const DelayArgs& a, hipStream_t s);
 // Writes the delay tables of a plan (DasArgs::rx_tab / tx_tabq layout) for
-// the tile shape (nt, px): rx always, tx for STAI (mode 0) when tx != null.
+// the tile shape (nt, px): rx always, tx when tx != null.
 hipError_t launch_delay_tables(int mode, int nt, int px, const DasArgs& a, uint32_t* rx,
                                uint32_t* tx, hipStream_t s);
 hipError_t launch_envelope(const float* bf, int F, int nz, int nx, float* env, float* col_max,

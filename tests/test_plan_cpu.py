@@ -72,10 +72,11 @@ def _tile_slots(w):
     return info["ntz"] * info["ntx"] * info["threads"] * info["px"]
 
 
-@pytest.mark.parametrize("name", ["stai_small", "pwi"])
+@pytest.mark.parametrize("name", ["stai_small", "pwi", "paper_pwi"])
 def test_delay_tables_add_one_word_per_slot_and_element(lib, name):
     """WF_PLAN_DELAY_TABLES adds, 256-byte aligned, 4 bytes per (pixel slot,
-    channel padded to 16) and, for STAI, per (pixel slot, transmit)."""
+    channel padded to 16) and per (pixel slot, transmit), the latter for
+    every tile shape but PWI on 1024 x 2 tiles."""
     import paper_1811_01566_amd as wf
     import phantom
     from wfhelp import scan_from_workload
@@ -86,11 +87,14 @@ def test_delay_tables_add_one_word_per_slot_and_element(lib, name):
     full = wf.plan_bytes(scan, w.n_s, delay_tables=True)
     slots = _tile_slots(w)
     rx = slots * math.ceil(w.n_ch / 16) * 16 * 4
-    tx = slots * w.n_tx * 4 if w.mode == "stai" else 0
+    info = wf.tile_info(scan, w.n_s, 1)
+    # transmit words for every tile shape but PWI on 1024 x 2 tiles
+    pwi_large = w.mode == "pwi" and info["threads"] == 1024 and info["px"] == 2
+    tx = 0 if pwi_large else slots * w.n_tx * 4
     align = lambda v: math.ceil(v / 256) * 256  # noqa: E731
     assert full - plain == align(rx) + align(tx)
-    if name == "pwi":  # 1024 x 512 grid, 128 channels: 256 MiB of receive words
-        assert full - plain == 256 << 20
+    if name == "pwi":  # 1024 x 512 grid on 1024 x 2 tiles, 128 channels: 256 MiB
+        assert pwi_large and full - plain == 256 << 20
 
 
 def test_unknown_plan_flags_are_refused(lib):

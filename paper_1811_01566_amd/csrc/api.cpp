@@ -251,66 +251,49 @@ constexpr size_t kLdsHard = 163840;
 #define WF_ADJ_TWO_SETS 1
 #endif
 
-bool choose_tile(const Geometry& g, const wf_acq* acq, const wf_grid* grid, TilePlan* best) {
-    // (threads, pixels per thread); 512 x 2 covers the same tiles as 256 x 4
-    // with twice the waves per workgroup, 1024 x 1 the same with four times
-    // the waves, 1024 x 2 twice the tile
-    const int shapes[5][2] = {{WF_DAS_ALLOW_1024 ? 1024 : 512, 2},
-                              {WF_DAS_ALLOW_1024 ? 1024 : 512, WF_DAS_ALLOW_1024 ? 1 : 2},
-                              {512, 2},
-                              {256, 4},
-                              {256, 1}};
-    // a plan must leave LDS for 8 resident waves per CU (two 256-thread
-    // workgroups, or one of 512 or 1024 threads); one with 4 is taken only
-    // when nothing else fits
-    for (int min_waves : {8, 4}) {
-        double best_score = -1.0;
-        for (const auto& sh : shapes) {
-            const int nt = sh[0], px = sh[1];
-            for (int tzl = 6; tzl >= 3; --tzl) {
-                const int tz = 1 << tzl;
-                const int txw = (nt * px) >> tzl;
-                const int ez = std::min(tz, grid->nz), ex = std::min(txw, grid->nx);
-                const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
-                const int span = (int)std::ceil(d) + 3;
-                const int nst = ((2 * span + 8) + 7) & ~7;
-                // windows of consecutive channels start 16 bytes apart
-                // modulo 128 (slot = 2 mod 16), so the 8 lanes that stage the
-                // same group of 8 consecutive channels store to distinct banks
-                const int slot = (((nst + span + 8) - 2 + 15) & ~15) + 2;
-                if (nst + span > 511) continue;
-                const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
-                if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
-                const size_t lds = das_lds_bytes(slot, acq->n_tx);
-                if (lds > kLdsHard || (int)(kLdsHard / lds) * (nt / 64) < min_waves) continue;
-                const int ntz = (grid->nz + tz - 1) / tz, ntx = (grid->nx + txw - 1) / txw;
-                // one frame's workgroups: the plan (window bases, so the
-                // rounding of the delays) must not depend on the frame count,
-                // or a batch and its frames one by one would differ
-                const double wgs = (double)ntz * ntx;
-                // pixels served per staged sample, discounted when there are
-                // too few workgroups to give every CU 16 waves; ties keep the
-                // earlier shape
-                const double fill = 256.0 * 1024.0 / nt;
-                const double reuse = (double)ez * ex / nst;
-                const double score = reuse * std::min(1.0, wgs / fill);
-                if (score > best_score * (1.0 + 1e-9)) {
-                    best_score = score;
-                    best->threads = nt;
-                    best->px = px;
-                    best->tz_log2 = tzl;
-                    best->span = span;
-                    best->nst = nst;
-                    best->slot = slot;
-                    best->lds = lds;
-                    best->ntz = ntz;
-                    best->ntx = ntx;
-                }
-            }
+// Tile plans a geometry can run: each (threads, pixels per thread) shape
+// and tile height whose window fits the gather's staging limits and whose
+// LDS leaves `min_waves` resident waves per CU.  Shapes: 1024 x 2 and 512 x 2
+// (two pixels a thread, 16 or 8 waves), 512 x 1 and 256 x 1 (half the tile,
+// a smaller window).  256 x 4 and 1024 x 1 cover the tiles of 512 x 2 with
+// fewer waves or one pixel a thread and measured slower on every geometry.
+std::vector<TilePlan> tile_candidates(const Geometry& g, const wf_acq* acq, const wf_grid* grid,
+                                      int min_waves) {
+    const int shapes[4][2] = {{1024, 2}, {512, 2}, {512, 1}, {256, 1}};
+    std::vector<TilePlan> out;
+    for (const auto& sh : shapes) {
+        const int nt = sh[0], px = sh[1];
+        if (nt == 1024 && !WF_DAS_ALLOW_1024) continue;
+        for (int tzl = 6; tzl >= 3; --tzl) {
+            const int tz = 1 << tzl;
+            const int txw = (nt * px) >> tzl;
+            const int ez = std::min(tz, grid->nz), ex = std::min(txw, grid->nx);
+            const double d = std::hypot((ez - 1) * g.dzs, (ex - 1) * g.dxs);
+            const int span = (int)std::ceil(d) + 3;
+            const int nst = ((2 * span + 8) + 7) & ~7;
+            // windows of consecutive channels start 16 bytes apart
+            // modulo 128 (slot = 2 mod 16), so the 8 lanes that stage the
+            // same group of 8 consecutive channels store to distinct banks
+            const int slot = (((nst + span + 8) - 2 + 15) & ~15) + 2;
+            if (nst + span > 511) continue;
+            const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
+            if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
+            const size_t lds = das_lds_bytes(slot, acq->n_tx);
+            if (lds > kLdsHard || (int)(kLdsHard / lds) * (nt / 64) < min_waves) continue;
+            TilePlan tp;
+            tp.threads = nt;
+            tp.px = px;
+            tp.tz_log2 = tzl;
+            tp.span = span;
+            tp.nst = nst;
+            tp.slot = slot;
+            tp.lds = lds;
+            tp.ntz = (grid->nz + tz - 1) / tz;
+            tp.ntx = (grid->nx + txw - 1) / txw;
+            out.push_back(tp);
         }
-        if (best_score > 0.0) return true;
     }
-    return false;
+    return out;
 }
 
 // LDS bytes of a gather workgroup staging pp passes per barrier.
@@ -604,18 +587,80 @@ std::string geometry_key(int mode, const wf_acq* acq, const wf_grid* grid, const
     return k;
 }
 
-// Tile plan and work split of a geometry whose `g` and `key` are filled.
-// The split comes from a dispatch simulation over the pass map: up to a few
-// milliseconds of host time on the largest grids.
+int das_passes_per_barrier(const TilePlan& tp, int T, int dtype);
+
+// Relative time per contribution of a tile plan and its split, a model
+// fitted to the gather's measured times on gfx950 (every shape and tile
+// height of the tile candidates, on STAI and PWI geometries from 128 x 128
+// to 2048 x 128 pixels and 11 to 128 transmits):
+//  - each staged window sample serves `reuse` pixels; staging it costs
+//    about 1.5 contributions;
+//  - a CU hides latency with 32 pixels in flight per lane slot (16 waves of
+//    two pixels); with fewer, the cost rises by up to 2x at none;
+//  - one pixel a thread shares no per-thread work (delay words, window
+//    bases) between pixels: 6 %;
+//  - a workgroup that takes a CU's LDS alone exposes its start (tables,
+//    first window) and end (partial-frame write) whenever others queue
+//    for the CU: about half the time of a 64-pass workgroup.
+// Residency counts the 16-bit RF gather (two passes per barrier on
+// 1024-thread tiles) so the plan does not depend on the RF type.
+// With sp null: the least cost any split can give (every resident slot
+// filled, no exposed start or end).
+double plan_cost(const TilePlan& tp, const SplitPlan* sp, int T) {
+    const int ez = 1 << tp.tz_log2;
+    const int ex = (tp.threads * tp.px) >> tp.tz_log2;
+    const double reuse = (double)ez * ex / tp.nst;
+    const size_t lds = das_gather_lds(tp, T, das_passes_per_barrier(tp, T, WF_RF_I16));
+    const int res = std::max(1, std::min((int)(kLdsHard / lds), 2048 / tp.threads));
+    const double items = !sp ? 256.0 * res
+                             : !sp->order.empty() ? (double)sp->order.size()
+                                                  : (double)tp.ntz * tp.ntx * sp->nsplit;
+    const double resident = std::min((double)res, std::max(1.0, items / 256.0));
+    const double lanes = tp.px * (tp.threads / 64) * resident;
+    double cost = (1.0 + 1.5 / reuse) * (1.0 + std::max(0.0, 32.0 - lanes) / 32.0);
+    if (tp.px == 1) cost *= 1.06;
+    if (res == 1 && sp)
+        cost *= 1.0 + 0.5 * 64.0 / ((double)sp->chunks * sp->txs) *
+                          std::max(0.0, 1.0 - 256.0 / items);
+    return cost;
+}
+
+// Tile plan and work split of a geometry whose `g` and `key` are filled:
+// of the tile candidates, each with its own split, the one of least
+// plan_cost (ties keep the one of lesser least cost).  Candidates must leave 8 resident
+// waves per CU; ones with 4 are taken only when nothing else fits.  Each
+// split comes from a dispatch simulation over the pass map: a few
+// milliseconds of host time per candidate on the largest grids.
 wf_status plan_core(const wf_acq* acq, const wf_grid* grid, PlanCore* c) {
-    if (!choose_tile(c->g, acq, grid, &c->tp))
-        return fail(WF_ERR_UNSUPPORTED,
-                    "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
-                    c->g.dzs, c->g.dxs);
-    if ((long long)c->tp.ntz * c->tp.ntx > 0x7FFFFFFF)
-        return fail(WF_ERR_UNSUPPORTED, "too many tiles");
-    c->sp = plan_split(c->mode, c->g, acq, grid, c->tp);
-    return WF_OK;
+    for (int min_waves : {8, 4}) {
+        const std::vector<TilePlan> cand = tile_candidates(c->g, acq, grid, min_waves);
+        // candidates in order of their least cost: a split is planned only
+        // for those that could still win
+        std::vector<std::pair<double, int>> order;
+        for (size_t i = 0; i < cand.size(); ++i)
+            if ((long long)cand[i].ntz * cand[i].ntx <= 0x7FFFFFFF)
+                order.emplace_back(plan_cost(cand[i], nullptr, acq->n_tx), (int)i);
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto& x, const auto& y) { return x.first < y.first; });
+        double best = 0.0;
+        bool found = false;
+        for (const auto& o : order) {
+            if (found && o.first >= best * (1.0 - 1e-9)) break;
+            const TilePlan& tp = cand[o.second];
+            SplitPlan sp = plan_split(c->mode, c->g, acq, grid, tp);
+            const double cost = plan_cost(tp, &sp, acq->n_tx);
+            if (!found || cost < best * (1.0 - 1e-9)) {
+                found = true;
+                best = cost;
+                c->tp = tp;
+                c->sp = std::move(sp);
+            }
+        }
+        if (found) return WF_OK;
+    }
+    return fail(WF_ERR_UNSUPPORTED,
+                "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
+                c->g.dzs, c->g.dxs);
 }
 
 // Geometry and key of a validated call (cheap: O(elements + transmits +

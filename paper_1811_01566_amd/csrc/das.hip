@@ -527,7 +527,7 @@ template <int MODE, typename RT, int NT, int PX, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
     constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
     // staged groups per lane: a pass stages at most 16 x 64 groups (nst <= 512)
-    constexpr int NG = (NT == 1024 && PX == 1) ? 1 : 2;
+    constexpr int NG = 2;
     if constexpr (OP == kOpValue) {
         if (a.F > 1) {
             if constexpr (kPairs)
@@ -540,18 +540,15 @@ hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
     return launch_one<MODE, RT, NT, PX, NG, OP, 1>(a, lds, s);
 }
 
-// (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 1024 x 1
-// (16 waves on the tile of 512 x 2), 512 x 2 (8 waves), 256 x 4 (4 waves,
-// the same tile again) or 256 x 1 (small tiles for coarse grids)
+// (threads, pixels per thread): 1024 x 2 (large tiles, 16 waves), 512 x 2
+// (8 waves), 512 x 1 (half the tile, 8 waves) or 256 x 1 (small tiles for
+// coarse grids)
 template <int MODE, typename RT, int OP>
 hipError_t launch_px(int nt, int px, int groups, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024)
-        return px == 1 ? launch_large<MODE, RT, 1024, 1, OP>(a, lds, s)
-                       : launch_large<MODE, RT, 1024, 2, OP>(a, lds, s);
-    if (nt == 512) return launch_large<MODE, RT, 512, 2, OP>(a, lds, s);
-    if (px == 4)
-        return groups <= 2 ? launch_one<MODE, RT, 256, 4, 2, OP>(a, lds, s)
-                           : launch_one<MODE, RT, 256, 4, 4, OP>(a, lds, s);
+    if (nt == 1024) return launch_large<MODE, RT, 1024, 2, OP>(a, lds, s);
+    if (nt == 512)
+        return px == 1 ? launch_large<MODE, RT, 512, 1, OP>(a, lds, s)
+                       : launch_large<MODE, RT, 512, 2, OP>(a, lds, s);
     return groups <= 2 ? launch_one<MODE, RT, 256, 1, 2, OP>(a, lds, s)
                        : launch_one<MODE, RT, 256, 1, 4, OP>(a, lds, s);
 }
@@ -622,9 +619,9 @@ hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s)
 }
 
 static bool shape_ok(int nt, int px, int groups) {
-    if (nt == 1024) return (px == 2 && groups <= 2) || (px == 1 && groups <= 1);
-    if (nt == 512) return px == 2 && groups <= 2;
-    return nt == 256 && (px == 4 || px == 1) && groups <= kMaxGroups;
+    if (nt == 1024) return px == 2 && groups <= 2;
+    if (nt == 512) return (px == 2 || px == 1) && groups <= 2;
+    return nt == 256 && px == 1 && groups <= kMaxGroups;
 }
 
 hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
@@ -664,11 +661,10 @@ hipError_t launch_tables(const DasArgs& a, uint32_t* rx, uint32_t* tx, hipStream
 template <int MODE>
 hipError_t launch_tables_shape(int nt, int px, const DasArgs& a, uint32_t* rx, uint32_t* tx,
                                hipStream_t s) {
-    if (nt == 1024) return px == 1 ? launch_tables<MODE, 1024, 1>(a, rx, tx, s)
-                                   : launch_tables<MODE, 1024, 2>(a, rx, tx, s);
-    if (nt == 512) return launch_tables<MODE, 512, 2>(a, rx, tx, s);
-    return px == 4 ? launch_tables<MODE, 256, 4>(a, rx, tx, s)
-                   : launch_tables<MODE, 256, 1>(a, rx, tx, s);
+    if (nt == 1024) return launch_tables<MODE, 1024, 2>(a, rx, tx, s);
+    if (nt == 512) return px == 1 ? launch_tables<MODE, 512, 1>(a, rx, tx, s)
+                                  : launch_tables<MODE, 512, 2>(a, rx, tx, s);
+    return launch_tables<MODE, 256, 1>(a, rx, tx, s);
 }
 
 hipError_t launch_delay_tables(int mode, int nt, int px, const DasArgs& a, uint32_t* rx,

@@ -56,15 +56,18 @@ def test_plan_equals_no_plan(wf_gpu, name):
 
 
 def _table_cases():
-    """Geometries over every tile shape and delay path: STAI small (256 x 1
+    """Geometries over every tile shape and delay path: STAI small (512 x 1
     tiles, split, work list), STAI with t0 != 0 and an f-number (transmit
     delays with a time origin, apodised receive words), a STAI sub-grid on
-    1024 x 1 tiles, PWI sub-grid (1024 x 2 tiles, two passes per barrier),
-    PWI deeper than its record, and the full 1024 x 512 PWI frame (1024 x 2
-    tiles; its oracle parity is the full-frame test's)."""
+    512 x 2 tiles, a coarse 256 x 128 STAI grid (256 x 1 tiles), PWI
+    sub-grid (1024 x 2 tiles, two passes per barrier), PWI deeper than its
+    record, and the full 1024 x 512 PWI frame (1024 x 2 tiles; its oracle
+    parity is the full-frame test's)."""
+    from phantom.configs import served_mix
     from wfhelp import deep_pwi
 
     full = lighter(phantom.get_workload("stai_full"), 2000)
+    coarse = next(w for w in served_mix() if w.name == "stai_n128_t16_s1024_256x128")
     return {
         "stai_small": phantom.get_workload("stai_small"),
         # (no pixel lies within 1e-4 of an aperture edge: at an exact tie
@@ -73,14 +76,15 @@ def _table_cases():
                                           z_min=4.05e-3, z_max=11.9e-3, f_number=1.17,
                                           t0=0.35e-6),
         "stai_full_sub": subgrid(full.with_(n_tx=48), 64, 192, 40, 96),
+        "stai_coarse": coarse,
         "pwi_sub": subgrid(lighter(phantom.get_workload("pwi")), 300, 128, 200, 96),
         "deep_pwi": deep_pwi(),
         "pwi_full": lighter(phantom.get_workload("pwi")),
     }
 
 
-@pytest.mark.parametrize("name", ["stai_small", "stai_t0_fnum", "stai_full_sub", "pwi_sub",
-                                  "deep_pwi", "pwi_full"])
+@pytest.mark.parametrize("name", ["stai_small", "stai_t0_fnum", "stai_full_sub", "stai_coarse",
+                                  "pwi_sub", "deep_pwi", "pwi_full"])
 def test_delay_tables_give_the_same_bits(wf_gpu, name):
     """A plan with the delay tables (the gathers read the receive and STAI
     transmit words) and one without (the gathers form them) give the same

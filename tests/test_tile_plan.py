@@ -26,10 +26,10 @@ def _check(w):
     assert info["lds_bytes"] <= LDS_LIMIT
     assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 32 * w.n_tx
     # staged groups of one pass fit the per-lane register staging (2 groups
-    # per lane on 512- and 1024-thread tiles of 2 pixels per lane, 1 with 1)
-    ng = 2 // info["px"] if nt >= 512 else 4
+    # per lane on 512- and 1024-thread tiles, 4 on 256-thread tiles)
+    ng = 2 if nt >= 512 else 4
     assert info["chunk"] * (nst // 8) <= ng * nt
-    assert (nt, info["px"]) in ((256, 4), (512, 2), (1024, 2), (1024, 1), (256, 1))
+    assert (nt, info["px"]) in ((1024, 2), (512, 2), (512, 1), (256, 1))
     assert info["tile_z"] * info["tile_x"] == nt * info["px"]
     assert nt % info["tile_z"] == 0
     assert info["ntz"] * info["tile_z"] >= w.nz > (info["ntz"] - 1) * info["tile_z"]

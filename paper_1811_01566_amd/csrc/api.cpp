@@ -276,7 +276,7 @@ std::vector<TilePlan> tile_candidates(const Geometry& g, const wf_acq* acq, cons
             // same group of 8 consecutive channels store to distinct banks
             const int slot = (((nst + span + 8) - 2 + 15) & ~15) + 2;
             if (nst + span > 511) continue;
-            const int max_groups = nt >= 512 ? 2 : wf::kMaxGroups;
+            const int max_groups = nt == 1024 ? 1 : nt == 512 ? 2 : wf::kMaxGroups;
             if (wf::kChunk * (nst / 8) > max_groups * nt) continue;
             const size_t lds = das_lds_bytes(slot, acq->n_tx);
             if (lds > kLdsHard || (int)(kLdsHard / lds) * (nt / 64) < min_waves) continue;

@@ -526,8 +526,9 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
 template <int MODE, typename RT, int NT, int PX, int OP>
 hipError_t launch_large(const DasArgs& a, size_t lds, hipStream_t s) {
     constexpr bool kPairs = NT == 1024 && sizeof(RT) == 2;
-    // staged groups per lane: a pass stages at most 16 x 64 groups (nst <= 512)
-    constexpr int NG = 2;
+    // staged groups per lane: a pass stages 16 x nst / 8 groups, and
+    // nst + span <= 511 keeps that below 1024
+    constexpr int NG = NT == 1024 ? 1 : 2;
     if constexpr (OP == kOpValue) {
         if (a.F > 1) {
             if constexpr (kPairs)
@@ -619,7 +620,7 @@ hipError_t launch_store(void* dst, const void* src, size_t bytes, hipStream_t s)
 }
 
 static bool shape_ok(int nt, int px, int groups) {
-    if (nt == 1024) return px == 2 && groups <= 2;
+    if (nt == 1024) return px == 2 && groups <= 1;
     if (nt == 512) return (px == 2 || px == 1) && groups <= 2;
     return nt == 256 && px == 1 && groups <= kMaxGroups;
 }

@@ -25,9 +25,9 @@ def _check(w):
     assert nst % 8 == 0
     assert info["lds_bytes"] <= LDS_LIMIT
     assert info["lds_bytes"] >= 2 * info["chunk"] * slot * 8 + 32 * w.n_tx
-    # staged groups of one pass fit the per-lane register staging (2 groups
-    # per lane on 512- and 1024-thread tiles, 4 on 256-thread tiles)
-    ng = 2 if nt >= 512 else 4
+    # staged groups of one pass fit the per-lane register staging (1 group
+    # per lane on 1024-thread tiles, 2 on 512-thread, 4 on 256-thread tiles)
+    ng = {1024: 1, 512: 2}.get(nt, 4)
     assert info["chunk"] * (nst // 8) <= ng * nt
     assert (nt, info["px"]) in ((1024, 2), (512, 2), (512, 1), (256, 1))
     assert info["tile_z"] * info["tile_x"] == nt * info["px"]

@@ -39,8 +39,8 @@
  *
  * Plans.  The DAS-shaped calls (wf_das_stai, wf_das_pwi, wf_das_dydc,
  * wf_das_adjoint) need a few KB of per-geometry device tables: the
- * per-transmit and per-channel delay constants and the work list of the
- * launch.  With a plan (wf_plan_build_*) they live in caller-owned device
+ * per-transmit and per-channel delay constants and the work lists of the
+ * launches (the adjoint may run its own tiles and work list).  With a plan (wf_plan_build_*) they live in caller-owned device
  * memory and the call neither allocates nor synchronises: it only launches
  * kernels on `stream`, so it may be captured into a HIP graph even for a
  * geometry never run before.  With plan = NULL the library keeps the tables

@@ -339,7 +339,9 @@ hipError_t launch_adj(const DasArgs& a, size_t lds, hipStream_t s) {
 
 template <int MODE, int NB>
 hipError_t launch_adj_nb(int nt, int px, const DasArgs& a, size_t lds, hipStream_t s) {
-    if (nt == 1024) return launch_adj<MODE, 1024, 2, NB>(a, lds, s);
+    if (nt == 1024)
+        return px == 1 ? launch_adj<MODE, 1024, 1, NB>(a, lds, s)
+                       : launch_adj<MODE, 1024, 2, NB>(a, lds, s);
     if (nt == 512)
         return px == 1 ? launch_adj<MODE, 512, 1, NB>(a, lds, s)
                        : launch_adj<MODE, 512, 2, NB>(a, lds, s);
@@ -357,8 +359,8 @@ hipError_t launch_adj_shape(int nt, int px, int nbuf, const DasArgs& a, size_t l
 
 hipError_t launch_das_adjoint(int mode, int nt, int px, int nbuf, const DasArgs& a,
                               size_t lds_bytes, hipStream_t s) {
-    // the gather's shapes: 1024 x 2, 512 x 2, 512 x 1, 256 x 1
-    if (!((nt == 1024 && px == 2) || (nt == 512 && (px == 2 || px == 1)) ||
+    // the gather's shapes (1024 x 2, 512 x 2, 512 x 1, 256 x 1) and 1024 x 1
+    if (!((nt == 1024 && (px == 2 || px == 1)) || (nt == 512 && (px == 2 || px == 1)) ||
           (nt == 256 && px == 1)))
         return hipErrorInvalidValue;
     return mode == 1 ? launch_adj_shape<1>(nt, px, nbuf, a, lds_bytes, s)

@@ -567,6 +567,8 @@ struct PlanCore {
     Geometry g;
     TilePlan tp;
     SplitPlan sp;
+    TilePlan atp;   // the adjoint's tiles (plan_adjoint)
+    SplitPlan asp;  // and their split
     std::string key;
 };
 
@@ -625,6 +627,40 @@ double plan_cost(const TilePlan& tp, const SplitPlan* sp, int T) {
     return cost;
 }
 
+// Tiles of the adjoint.  It flushes every (transmit, channel, tile) window
+// to its workspace and sums them into the RF gradient, so its cost grows
+// with the windows of a frame (tiles x transmits x channels x nst), and its
+// LDS scatter runs best with 16 waves a workgroup.  Measured: STAI full
+// 1.66 ms on 1024 x 1 threads over 64 x 16 tiles against 2.55 ms on the
+// gather's 512 x 1 over 32 x 16; paper STAI 5.08 ms on 1024 x 1 against
+// 5.69 ms on 512 x 2 over the same tiles.  So it keeps the gather's tiles
+// when they have 1024 threads, else takes the 1024-pixel candidate of most
+// reuse run by 1024 x 1 threads, else the gather's tiles; the split is
+// planned for its own tiles.
+void plan_adjoint(PlanCore* c, const wf_acq* acq, const wf_grid* grid) {
+    c->atp = c->tp;
+    c->asp = c->sp;
+    if (c->tp.threads == 1024 || !WF_DAS_ALLOW_1024) return;
+    const TilePlan* best = nullptr;
+    double best_reuse = 0.0;
+    const std::vector<TilePlan> cand = tile_candidates(c->g, acq, grid, 8);
+    for (const TilePlan& tp : cand) {
+        if (tp.threads * tp.px != 1024) continue;
+        const int ez = std::min(1 << tp.tz_log2, grid->nz);
+        const int ex = std::min(1024 >> tp.tz_log2, grid->nx);
+        const double reuse = (double)ez * ex / tp.nst;
+        if (reuse > best_reuse * (1.0 + 1e-9)) {
+            best_reuse = reuse;
+            best = &tp;
+        }
+    }
+    if (!best) return;
+    c->atp = *best;
+    c->atp.threads = 1024;
+    c->atp.px = 1;
+    c->asp = plan_split(c->mode, c->g, acq, grid, c->atp);
+}
+
 // Tile plan and work split of a geometry whose `g` and `key` are filled:
 // of the tile candidates, each with its own split, the one of least
 // plan_cost (ties keep the one of lesser least cost).  Candidates must leave 8 resident
@@ -656,7 +692,10 @@ wf_status plan_core(const wf_acq* acq, const wf_grid* grid, PlanCore* c) {
                 c->sp = std::move(sp);
             }
         }
-        if (found) return WF_OK;
+        if (found) {
+            plan_adjoint(c, acq, grid);
+            return WF_OK;
+        }
     }
     return fail(WF_ERR_UNSUPPORTED,
                 "pixel spacing (%.3g x %.3g samples) too coarse for the DAS tile window",
@@ -684,13 +723,14 @@ wf_status make_core(int mode, const wf_probe* probe, const wf_acq* acq, const in
 }
 
 // Device tables of a plan, inside one block of device memory:
-// [TxConst x T][ChConst x C][int x work-list items] and, in plans built with
-// delay tables, [receive delay words][transmit delay words]; each part
-// 256-byte aligned.
+// [TxConst x T][ChConst x C][int x work-list items][int x the adjoint's
+// work-list items] and, in plans built with delay tables, [receive delay
+// words][transmit delay words]; each part 256-byte aligned.
 struct DevTables {
     const wf::TxConst* tx = nullptr;
     const wf::ChConst* ch = nullptr;
     const int* items = nullptr;       // null when the plan has no work list
+    const int* aitems = nullptr;      // the adjoint's (null: none)
     const uint32_t* rx_q = nullptr;   // receive delay table (null: none)
     const uint32_t* tx_q = nullptr;   // transmit delay table (null: none)
 };
@@ -699,11 +739,11 @@ constexpr size_t kTableAlign = 256;
 size_t align_up(size_t v) { return (v + kTableAlign - 1) & ~(kTableAlign - 1); }
 
 struct TableLayout {
-    size_t ch, items, rx, tx, total;
+    size_t ch, items, aitems, rx, tx, total;
 };
 
 void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
-               wf::DasArgs* a);
+               wf::DasArgs* a, const TilePlan* tiles = nullptr);
 
 // Words of the delay tables (DasArgs::rx_tab, tx_tabq): per tile and pixel
 // slot, 16 receive words per channel chunk and one transmit word
@@ -722,7 +762,8 @@ TableLayout table_layout(const PlanCore& c, bool delay_tables) {
     TableLayout L;
     L.ch = align_up(c.g.tx.size() * sizeof(wf::TxConst));
     L.items = align_up(L.ch + c.g.ch.size() * sizeof(wf::ChConst));
-    L.rx = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
+    L.aitems = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
+    L.rx = align_up(L.aitems + std::max<size_t>(1, c.asp.order.size()) * sizeof(int));
     L.tx = L.rx + (delay_tables ? align_up(rx_table_words(c) * 4) : 0);
     L.total = L.tx + (delay_tables ? align_up(tx_table_words(c) * 4) : 0);
     return L;
@@ -740,11 +781,15 @@ wf_status upload_tables(const PlanCore& c, void* mem, bool delay_tables, const w
         e = wf::launch_store(m + L.ch, c.g.ch.data(), c.g.ch.size() * sizeof(wf::ChConst), s);
     if (e == hipSuccess && !c.sp.order.empty())
         e = wf::launch_store(m + L.items, c.sp.order.data(), c.sp.order.size() * sizeof(int), s);
+    if (e == hipSuccess && !c.asp.order.empty())
+        e = wf::launch_store(m + L.aitems, c.asp.order.data(), c.asp.order.size() * sizeof(int),
+                             s);
     if (e != hipSuccess) return hip_fail(e, "plan table upload");
     DevTables t;
     t.tx = reinterpret_cast<const wf::TxConst*>(m);
     t.ch = reinterpret_cast<const wf::ChConst*>(m + L.ch);
     t.items = c.sp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.items);
+    t.aitems = c.asp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.aitems);
     if (delay_tables) {
         uint32_t* rx = reinterpret_cast<uint32_t*>(m + L.rx);
         uint32_t* tx = tx_table_words(c) ? reinterpret_cast<uint32_t*>(m + L.tx) : nullptr;
@@ -799,11 +844,14 @@ wf_status prepare_kernels(const PlanCore& c, const wf_acq* acq, const wf_grid* g
                 e = wf::launch_das_dydc(c.mode, dtype, tp.threads, tp.px, groups, a, lds, 0);
             if (e != hipSuccess) return hip_fail(e, "DAS kernel attributes");
         }
+    const TilePlan& atp = c.atp;
+    fill_args(c, DevTables{}, acq, grid, &a, &atp);
+    a.prepare_only = 1;
     a.F = 1;
-    const int nbuf = adjoint_sets(tp, T);
+    const int nbuf = adjoint_sets(atp, T);
     hipError_t e = wf::launch_das_adjoint(
-        c.mode, tp.threads, tp.px, nbuf, a,
-        wf::das_lds(wf::das_adjoint_nbuf(nbuf), tp.slot, T).total, 0);
+        c.mode, atp.threads, atp.px, nbuf, a,
+        wf::das_lds(wf::das_adjoint_nbuf(nbuf), atp.slot, T).total, 0);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel attributes");
     return WF_OK;
 }
@@ -1016,10 +1064,12 @@ wf_status query_core(int mode, const wf_probe* probe, const wf_acq* acq, const i
 }
 
 // Kernel arguments of a plan (frames, RF, outputs and split set by callers).
+// Arguments of a launch on the plan's gather tiles, or on `tiles` (the
+// adjoint's), which then get no delay tables (those are the gather's).
 void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
-               wf::DasArgs* a) {
+               wf::DasArgs* a, const TilePlan* tiles) {
     const Geometry& g = c.g;
-    const TilePlan& tp = c.tp;
+    const TilePlan& tp = tiles ? *tiles : c.tp;
     *a = wf::DasArgs{};
     a->F = acq->n_frames;
     a->T = acq->n_tx;
@@ -1054,8 +1104,8 @@ void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const w
     a->neg_inv_c = (float)(-1.0 / acq->c);
     a->tx_tab = t.tx;
     a->ch_tab = t.ch;
-    a->rx_tab = t.rx_q;
-    a->tx_tabq = t.tx_q;
+    a->rx_tab = tiles ? nullptr : t.rx_q;
+    a->tx_tabq = tiles ? nullptr : t.tx_q;
 }
 
 // Checks of the buffers of a DAS-shaped call (after check_geometry).
@@ -1278,7 +1328,7 @@ wf_status wf_das_workspace(int32_t mode, const wf_probe* probe, const wf_acq* ac
 // Workspace of the two-stage adjoint for one frame: every (transmit,
 // channel, tile) window (nst + 1 floats) and its first sample (int).
 size_t adjoint_ws_bytes(const PlanCore& c) {
-    const TilePlan& tp = c.tp;
+    const TilePlan& tp = c.atp;
     const size_t slots = (size_t)c.n_tx * c.n_ch * tp.ntz * tp.ntx;
     return slots * (size_t)(tp.nst + 1) * 4 + slots * 4 + 256 + 256;  // + max |g|
 }
@@ -1324,8 +1374,8 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     if ((st = resolve(mode, probe, acq, tx, ang, tref, grid, plan, (hipStream_t)stream, &lk,
                       &r)) != WF_OK)
         return st;
-    const TilePlan& tp = r.core->tp;
-    const SplitPlan& sp = r.core->sp;
+    const TilePlan& tp = r.core->atp;
+    const SplitPlan& sp = r.core->asp;
     const size_t need = adjoint_ws_bytes(*r.core);
     if (workspace_bytes < need)
         return fail(WF_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
@@ -1333,7 +1383,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     if (overlaps(workspace, need, grad_rf, rf_bytes_of(acq)) || overlaps(workspace, need, g, gbytes))
         return fail(WF_ERR_INVALID_ARG, "workspace overlaps g or grad_rf");
     wf::DasArgs a;
-    fill_args(*r.core, r.t, acq, grid, &a);
+    fill_args(*r.core, r.t, acq, grid, &a, &tp);
     const size_t slots = (size_t)acq->n_tx * acq->n_ch * tp.ntz * tp.ntx;
     a.ntiles = tp.ntz * tp.ntx;
     a.ws_win = static_cast<float*>(workspace);
@@ -1352,7 +1402,7 @@ wf_status wf_das_adjoint(int32_t mode, const wf_probe* probe, const wf_acq* acq,
     const long long all_items = (long long)a.ntiles * sp.nsplit;
     const bool skipped = !sp.order.empty() && (long long)sp.order.size() < all_items;
     if (!sp.order.empty() && (sp.nsplit > 1 || skipped)) {
-        a.items = r.t.items;
+        a.items = r.t.aitems;
         a.nitems = (int)sp.order.size();
     }
     float no_window;

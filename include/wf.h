@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define WF_ABI_VERSION 7
+#define WF_ABI_VERSION 8
 
 typedef enum {
     WF_OK = 0,
@@ -307,14 +307,17 @@ wf_status wf_dot(const float* a, const float* b, int64_t n, float* out, void* st
 
 /*
  * Launch plan the DAS calls would use for this geometry (host only; touches
- * no device).  info (HOST int32[16]) receives: pixels per lane, tile depth,
+ * no device).  info (HOST int32[20]) receives: pixels per lane, tile depth,
  * tile width, window-local delay clamp (samples), staged window entries,
  * LDS entries per window, LDS bytes per workgroup of wf_das (twice the
  * window buffers where it stages two passes per barrier), tiles along z, tiles
  * along x, channels per pass, threads per workgroup, then the work split
  * used when the caller passes wf_das_workspace's bytes: items per tile,
  * channel chunks per item, transmit splits, transmits per item, and the
- * workgroups launched per frame (items that run no pass are left out).
+ * workgroups launched per frame (items that run no pass are left out);
+ * then the adjoint's launch (wf_das_adjoint runs its own tiles where the
+ * gather's are smaller than 1024 threads): threads per workgroup, pixels
+ * per lane, tile depth, items per tile.
  * mode 0 = STAI, 1 = PWI.  Returns WF_ERR_UNSUPPORTED when no tile shape
  * fits (as the DAS calls would).
  */

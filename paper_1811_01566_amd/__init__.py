@@ -393,7 +393,8 @@ def das_pwi(rf, scan: Scan, out=None, workspace=None, stream=None, plan=None):
 
 TILE_INFO_FIELDS = ("px", "tile_z", "tile_x", "span", "nst", "slot", "lds_bytes", "ntz", "ntx",
                     "chunk", "threads", "nsplit", "split_chunks", "split_tx_parts",
-                    "split_tx", "workgroups")
+                    "split_tx", "workgroups", "adjoint_threads", "adjoint_px",
+                    "adjoint_tile_z", "adjoint_nsplit")
 
 
 def tile_info(scan: Scan, n_s: int, n_frames: int = 1, dtype: int = 0) -> dict:

@@ -13,7 +13,7 @@ WF_ERR_INVALID_ARG = -1
 WF_ERR_UNSUPPORTED = -2
 WF_ERR_DEVICE = -3
 WF_ERR_WORKSPACE = -4
-WF_ABI_VERSION = 7
+WF_ABI_VERSION = 8
 WF_PLAN_DELAY_TABLES = 1  # plan flag: window-local delay tables in the plan
 
 WF_RF_I16, WF_RF_F16, WF_RF_F32 = 0, 1, 2

@@ -1590,6 +1590,10 @@ wf_status wf_das_tile_info(int32_t mode, const wf_probe* probe, const wf_acq* ac
     info[13] = sp.nts;
     info[14] = sp.txs;
     info[15] = (int32_t)(listed ? (long long)sp.order.size() : all_items);
+    info[16] = c->atp.threads;
+    info[17] = c->atp.px;
+    info[18] = 1 << c->atp.tz_log2;
+    info[19] = c->asp.nsplit;
     return ok();
 }
 

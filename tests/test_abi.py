@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_abi_version(lib):
     from paper_1811_01566_amd import _lib
 
-    assert lib.wf_abi_version() == _lib.WF_ABI_VERSION == 7
+    assert lib.wf_abi_version() == _lib.WF_ABI_VERSION == 8
 
 
 def _geom(n_elem=8, n_tx=4, n_ch=8, n_s=256):

@@ -42,6 +42,10 @@ CASES = {
     # split into items, with items that run nothing left out of the work list
     "stai_small": lambda: phantom.get_workload("stai_small"),
     "deep_pwi": deep_pwi,
+    # the gather runs 512 x 2 tiles, the adjoint its own 1024 x 1 tiles,
+    # split and work list
+    "stai_own_tiles": lambda: subgrid(lighter(phantom.get_workload("stai_full"), 2000).with_(
+        n_tx=16), 64, 128, 40, 64),
 }
 
 
@@ -52,6 +56,11 @@ def test_adjoint_matches_oracle_and_dot_product(wf_gpu, name):
     if name in ("stai_small", "deep_pwi"):
         info = wf_gpu.tile_info(scan_from_workload(w), w.n_s)
         assert info["workgroups"] < info["ntz"] * info["ntx"] * info["nsplit"]
+    if name == "stai_own_tiles":
+        info = wf_gpu.tile_info(scan_from_workload(w), w.n_s)
+        assert (info["threads"], info["px"]) == (512, 2)
+        assert (info["adjoint_threads"], info["adjoint_px"]) == (1024, 1)
+        assert info["adjoint_nsplit"] > 1
     rng = np.random.default_rng(4)
     g = rng.normal(size=(w.nz, w.nx)).astype(np.float32)
     r = rng.normal(size=(w.n_tx, w.n_ch, w.n_s)).astype(np.float32)

@@ -100,3 +100,22 @@ def test_split_plans(name):
 def test_split_plans_served_mix():
     for w in served_mix()[::7]:
         _check_split(w)
+
+
+@pytest.mark.parametrize("name", ["stai_small", "stai_full", "pwi", "paper_stai", "paper_pwi"])
+def test_adjoint_tiles(name):
+    """The adjoint keeps the gather's tiles when they have 1024 threads, else
+    runs a 1024-pixel tile candidate with 1024 x 1 threads where one fits
+    (STAI full: the 64 x 16 tile), else the gather's tiles."""
+    w = phantom.get_workload(name)
+    info = wf.tile_info(scan_from_workload(w), w.n_s, 1)
+    adj = (info["adjoint_threads"], info["adjoint_px"], info["adjoint_tile_z"])
+    gather = (info["threads"], info["px"], info["tile_z"])
+    if info["threads"] == 1024:
+        assert adj == gather and info["adjoint_nsplit"] == info["nsplit"]
+    else:
+        assert adj == gather or adj[:2] == (1024, 1)
+    if name == "stai_full":
+        assert gather[:2] == (512, 1) and adj == (1024, 1, 64)
+    if name == "pwi":
+        assert adj == (1024, 2, 64)

@@ -724,23 +724,51 @@ wf_status make_core(int mode, const wf_probe* probe, const wf_acq* acq, const in
 
 // Device tables of a plan, inside one block of device memory:
 // [TxConst x T][ChConst x C][int x work-list items][int x the adjoint's
-// work-list items] and, in plans built with delay tables, [receive delay
-// words][transmit delay words]; each part 256-byte aligned.
+// work-list items][uint64 x tiles: the splits each tile runs, for split
+// plans that leave items out] and, in plans built with delay tables,
+// [receive delay words][transmit delay words]; each part 256-byte aligned.
 struct DevTables {
     const wf::TxConst* tx = nullptr;
     const wf::ChConst* ch = nullptr;
     const int* items = nullptr;       // null when the plan has no work list
     const int* aitems = nullptr;      // the adjoint's (null: none)
+    const uint64_t* masks = nullptr;  // splits that run, per tile (null: all)
     const uint32_t* rx_q = nullptr;   // receive delay table (null: none)
     const uint32_t* tx_q = nullptr;   // transmit delay table (null: none)
 };
+
+int log2_of(int v) {  // v a power of two
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
 
 constexpr size_t kTableAlign = 256;
 size_t align_up(size_t v) { return (v + kTableAlign - 1) & ~(kTableAlign - 1); }
 
 struct TableLayout {
-    size_t ch, items, aitems, rx, tx, total;
+    size_t ch, items, aitems, masks, rx, tx, total;
 };
+
+// Per tile (z fastest, as the split reduce reads them) the splits whose
+// item is on the work list; empty where every item runs or none is split.
+std::vector<uint64_t> split_masks(const PlanCore& c) {
+    const SplitPlan& sp = c.sp;
+    const long long tiles = (long long)c.tp.ntz * c.tp.ntx;
+    if (sp.nsplit == 1 || sp.order.empty() || (long long)sp.order.size() == tiles * sp.nsplit)
+        return {};
+    std::vector<uint64_t> m((size_t)tiles, 0);
+    const bool xcd = WF_DAS_XCD_ORDER && tiles % 8 == 0;
+    const int per = (int)(tiles >> 3);
+    for (int item : sp.order) {
+        int tile = item / sp.nsplit;
+        const int split = item - tile * sp.nsplit;
+        // the kernel's remap; the result, tzi + ntz txi, is the reduce's index
+        if (xcd) tile = (tile & 7) * per + (tile >> 3);
+        m[(size_t)tile] |= 1ull << split;
+    }
+    return m;
+}
 
 void fill_args(const PlanCore& c, const DevTables& t, const wf_acq* acq, const wf_grid* grid,
                wf::DasArgs* a, const TilePlan* tiles = nullptr);
@@ -763,7 +791,8 @@ TableLayout table_layout(const PlanCore& c, bool delay_tables) {
     L.ch = align_up(c.g.tx.size() * sizeof(wf::TxConst));
     L.items = align_up(L.ch + c.g.ch.size() * sizeof(wf::ChConst));
     L.aitems = align_up(L.items + std::max<size_t>(1, c.sp.order.size()) * sizeof(int));
-    L.rx = align_up(L.aitems + std::max<size_t>(1, c.asp.order.size()) * sizeof(int));
+    L.masks = align_up(L.aitems + std::max<size_t>(1, c.asp.order.size()) * sizeof(int));
+    L.rx = align_up(L.masks + std::max<size_t>(1, split_masks(c).size()) * sizeof(uint64_t));
     L.tx = L.rx + (delay_tables ? align_up(rx_table_words(c) * 4) : 0);
     L.total = L.tx + (delay_tables ? align_up(tx_table_words(c) * 4) : 0);
     return L;
@@ -784,12 +813,16 @@ wf_status upload_tables(const PlanCore& c, void* mem, bool delay_tables, const w
     if (e == hipSuccess && !c.asp.order.empty())
         e = wf::launch_store(m + L.aitems, c.asp.order.data(), c.asp.order.size() * sizeof(int),
                              s);
+    const std::vector<uint64_t> masks = split_masks(c);
+    if (e == hipSuccess && !masks.empty())
+        e = wf::launch_store(m + L.masks, masks.data(), masks.size() * sizeof(uint64_t), s);
     if (e != hipSuccess) return hip_fail(e, "plan table upload");
     DevTables t;
     t.tx = reinterpret_cast<const wf::TxConst*>(m);
     t.ch = reinterpret_cast<const wf::ChConst*>(m + L.ch);
     t.items = c.sp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.items);
     t.aitems = c.asp.order.empty() ? nullptr : reinterpret_cast<const int*>(m + L.aitems);
+    t.masks = masks.empty() ? nullptr : reinterpret_cast<const uint64_t*>(m + L.masks);
     if (delay_tables) {
         uint32_t* rx = reinterpret_cast<uint32_t*>(m + L.rx);
         uint32_t* tx = tx_table_words(c) ? reinterpret_cast<uint32_t*>(m + L.tx) : nullptr;
@@ -1149,21 +1182,32 @@ wf_status launch_gather(int mode, int op, const void* rf, const wf_acq* acq, con
         a.split_tx = sp.txs;
     }
     // work list: the plan's non-empty items, heaviest first, when the split
-    // it was made for is the one that runs; outputs of the items it leaves
-    // out are cleared first (a fill kernel: the call may be captured)
-    // (a grid whose every tile runs, unsplit, keeps the plain tile order)
+    // it was made for is the one that runs.  The split reduce leaves out the
+    // partial frames of the items the list leaves out; unsplit, their tiles
+    // of the output are cleared first (a fill kernel: the call may be
+    // captured).  A grid whose every tile runs, unsplit, keeps the plain
+    // tile order.
     const long long all_items = (long long)tp.ntz * tp.ntx * sp.nsplit;
     const bool listed = split ? !sp.order.empty()
                               : sp.nsplit == 1 && !sp.order.empty() &&
                                     (long long)sp.order.size() < all_items;
+    wf::SplitMasks masks{};
     if (listed) {
         a.items = t.items;
         a.nitems = (int)sp.order.size();
         if ((long long)sp.order.size() < all_items) {
-            float* clear = split ? a.partial : out;
-            const size_t n = (split ? (size_t)sp.nsplit : 1) * (out_bytes / 4);
-            hipError_t e = wf::launch_fill(clear, n, 0.0f, stream);
-            if (e != hipSuccess) return hip_fail(e, "fill launch");
+            if (split) {
+                if (!t.masks) return fail(WF_ERR_INVALID_ARG, "plan tables lack the split masks");
+                masks.masks = t.masks;
+                masks.npix = grid->nz * grid->nx;
+                masks.nx = grid->nx;
+                masks.ntz = tp.ntz;
+                masks.tz_log2 = tp.tz_log2;
+                masks.txw_log2 = log2_of((tp.threads * tp.px) >> tp.tz_log2);
+            } else {
+                hipError_t e = wf::launch_fill(out, out_bytes / 4, 0.0f, stream);
+                if (e != hipSuccess) return hip_fail(e, "fill launch");
+            }
         }
     }
     // value and d y / d c gathers share the tile plan and the LDS layout;
@@ -1175,7 +1219,7 @@ wf_status launch_gather(int mode, int op, const void* rf, const wf_acq* acq, con
                            : wf::launch_das_dydc(mode, acq->dtype, tp.threads, tp.px,
                                                  groups_of(a, tp), a, lds, stream);
     if (e == hipSuccess && a.partial)
-        e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, stream);
+        e = wf::launch_split_reduce(a.partial, a.nsplit, out_bytes / 4, out, masks, stream);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "DAS kernel launch" : "dy/dc kernel launch");
     return ok();
 }

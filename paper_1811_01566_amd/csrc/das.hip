@@ -565,12 +565,26 @@ hipError_t launch_mode(int dtype, int nt, int px, int groups, const DasArgs& a, 
 }
 
 // Sum of the channel-split partial frames, in split order (deterministic).
+// Splits whose item did not run wrote nothing and are left out of their
+// tile's sum (where every item would have added exact zeros).
 __global__ void __launch_bounds__(256)
     split_reduce_kernel(const float* __restrict__ partial, int nsplit, size_t n,
-                        float* __restrict__ out) {
+                        float* __restrict__ out, const SplitMasks m) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        float v = partial[i];
-        for (int k = 1; k < nsplit; ++k) v += partial[(size_t)k * n + i];
+        uint64_t ran = ~0ull;
+        if (m.masks) {
+            const int p = (int)(i % (size_t)m.npix);
+            const int iz = p / m.nx, ix = p - (p / m.nx) * m.nx;
+            ran = m.masks[(ix >> m.txw_log2) * m.ntz + (iz >> m.tz_log2)];
+        }
+        float v = 0.0f;
+        bool first = true;
+        for (int k = 0; k < nsplit; ++k)
+            if ((ran >> k) & 1ull) {
+                const float x = partial[(size_t)k * n + i];
+                v = first ? x : v + x;
+                first = false;
+            }
         out[i] = v;
     }
 }
@@ -626,11 +640,12 @@ static bool shape_ok(int nt, int px, int groups) {
 }
 
 hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
-                               hipStream_t s) {
+                               const SplitMasks& m, hipStream_t s) {
+    if (nsplit < 1 || nsplit > 64 || (m.masks && m.npix <= 0)) return hipErrorInvalidValue;
     size_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
-                       nsplit, n, out);
+                       nsplit, n, out, m);
     return hipGetLastError();
 }
 

@@ -129,8 +129,15 @@ hipError_t launch_das(int mode, int dtype, int nt, int px, int groups, const Das
                       size_t lds_bytes, hipStream_t s);
 hipError_t launch_das_dydc(int mode, int dtype, int nt, int px, int groups, const DasArgs& a,
                            size_t lds_bytes, hipStream_t s);
+// Which splits of a tile ran, for the split reduce: masks[txi * ntz + tzi]
+// has bit k set when split k of tile (tzi, txi) wrote its partial frame
+// (masks = null: every split ran).
+struct SplitMasks {
+    const uint64_t* masks;
+    int npix, nx, ntz, tz_log2, txw_log2;
+};
 hipError_t launch_split_reduce(const float* partial, int nsplit, size_t n, float* out,
-                               hipStream_t s);
+                               const SplitMasks& m, hipStream_t s);
 // nbuf: window sets of the adjoint (1 or 2; lds_bytes must hold them)
 hipError_t launch_das_adjoint(int mode, int nt, int px, int nbuf, const DasArgs& a,
                               size_t lds_bytes, hipStream_t s);

@@ -108,12 +108,7 @@ enum : int {
 // of two frames of a transmit (FG > 1), are staged into two of four LDS
 // buffers per barrier, halving the barriers where one workgroup fills a
 // CU; the accumulation order is unchanged.
-// The gather reads its delays from the plan's delay tables where it has
-// them (DasArgs::rx_tab, and tx_tabq for the shapes of das_tx_words), else
-// forms them.  TAB = true fixes that at compile time (PWI launches with
-// tables: 10 VGPRs fewer); TAB = false tests it at run time (measured
-// faster for STAI, 0.41 against 0.44 ms on the 1024 x 256 frame).
-template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP, bool TAB>
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP>
 __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     static_assert(PP == 1 || (PP == 2 && FG % 2 == 0) || (PP == 2 && FG == 1),
                   "frame pairs need an even frame group");
@@ -163,8 +158,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                 rq[k][4 * q + 3] = v.w;
             }
     };
-    const bool tab = TAB || a.rx_tab != nullptr;
-    if (tab && cb < ce) load_rq(cb);
+    if (a.rx_tab && cb < ce) load_rq(cb);
     // per-transmit tables and the first chunk's bases (the last kChunk
     // threads), published by the first chunk's barrier
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
@@ -242,7 +236,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // pass (txr), copied aside when it is committed (txc); the plan
         // holds them for every shape but PWI on 1024 x 2 tiles
         constexpr bool kTxTab = FG == 1 && das_tx_words(MODE, NT, PX);
-        const bool tx_tab = kTxTab && (TAB || a.tx_tabq != nullptr);
+        const bool tx_tab = kTxTab && a.tx_tabq != nullptr;
         uint32_t txr[PP][PX], txc[PP][PX];
         auto issue = [&](int t, int g, int h) {  // pass t of frame frame0 + g into raw[h]
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
@@ -313,7 +307,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         int t1 = PP == 2 && FG == 1 ? next_active(t + 1) : te;  // second transmit of a pair
         if (PP == 2 && FG == 1 && t1 < te) issue(t1, 0, PP - 1);
         if (PP == 2 && FG > 1) issue(t, 1, PP - 1);  // second frame of a pair
-        if (tab) {
+        if (a.rx_tab) {
             if (c0 != cb) load_rq(c0);
         } else {
             rx_delays<PX>(a, p, c0, bj, rq);
@@ -514,26 +508,13 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     // allocation would leave them outside the LDS it is given
     if (a.pp != PP || !das_lds_fits(lds, das_gather_nbuf(PP), a.slot, a.T))
         return hipErrorInvalidValue;
-    // PWI launches with delay tables take the compile-time variant; a
-    // prepared plan sets the LDS limit of both, so its calls, with or
-    // without the tables, make no attribute call
-    constexpr bool kFixed = MODE == 1;
-    const bool fixed = kFixed && a.rx_tab != nullptr;
-    hipError_t e = hipSuccess;
-    if (kFixed && (a.prepare_only || fixed))
-        e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, kFixed>, lds);
-    if (e == hipSuccess && (a.prepare_only || !fixed))
-        e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, false>, lds);
+    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
     if (e != hipSuccess || a.prepare_only) return e;
     const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, groups, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), groups, (unsigned)a.nsplit);
-    if (fixed)
-        hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, kFixed>), grid,
-                           dim3(NT), lds, s, a);
-    else
-        hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, false>), grid,
-                           dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>), grid, dim3(NT), lds, s,
+                       a);
     return hipGetLastError();
 }
 

@@ -119,3 +119,29 @@ def test_adjoint_tiles(name):
         assert gather[:2] == (512, 1) and adj == (1024, 1, 64)
     if name == "pwi":
         assert adj == (1024, 2, 64)
+
+
+# The tile shape and height that ran fastest in a same-box sweep of every
+# candidate (DAS launch time on MI355X), per geometry; the planner's cost
+# model must keep choosing them.
+MEASURED_BEST = {
+    "stai_full": (512, 1, 32),
+    "paper_stai": (512, 2, 64),
+    "stai_small": (512, 1, 16),
+    "paper_pwi": (512, 1, 64),
+    "pwi": (1024, 2, 64),
+    "stai_n128_t32_s1024_1024x512": (512, 2, 64),
+    "stai_n64_t64_s1024_256x128": (512, 1, 32),
+    "stai_n192_t64_s1024_512x256": (512, 2, 64),
+    "pwi_n128_t128_s2048_512x256": (512, 2, 64),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MEASURED_BEST))
+def test_planner_picks_the_measured_best_tiles(name):
+    from phantom.configs import served_pool
+
+    pool = {w.name: w for w in served_pool(8)}
+    w = pool[name] if name in pool else phantom.get_workload(name)
+    info = wf.tile_info(scan_from_workload(w), w.n_s, 1)
+    assert (info["threads"], info["px"], info["tile_z"]) == MEASURED_BEST[name]

@@ -577,14 +577,22 @@ __global__ void __launch_bounds__(256)
             const int iz = p / m.nx, ix = p - (p / m.nx) * m.nx;
             ran = m.masks[(ix >> m.txw_log2) * m.ntz + (iz >> m.tz_log2)];
         }
+        // eight partial frames loaded at a time, then added in split order
+        // (a frame that did not run is loaded but never added)
         float v = 0.0f;
         bool first = true;
-        for (int k = 0; k < nsplit; ++k)
-            if ((ran >> k) & 1ull) {
-                const float x = partial[(size_t)k * n + i];
-                v = first ? x : v + x;
-                first = false;
-            }
+        for (int k0 = 0; k0 < nsplit; k0 += 8) {
+            float x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                x[j] = k0 + j < nsplit ? partial[(size_t)(k0 + j) * n + i] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < nsplit && ((ran >> (k0 + j)) & 1ull)) {
+                    v = first ? x[j] : v + x[j];
+                    first = false;
+                }
+        }
         out[i] = v;
     }
 }

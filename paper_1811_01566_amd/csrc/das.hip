@@ -108,7 +108,11 @@ enum : int {
 // of two frames of a transmit (FG > 1), are staged into two of four LDS
 // buffers per barrier, halving the barriers where one workgroup fills a
 // CU; the accumulation order is unchanged.
-template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP>
+// TAB = true: the launch has the plan's delay tables (rx_tab, and tx_tabq
+// for the shapes of das_tx_words), fixed at compile time; TAB = false
+// tests for them at run time.  Only PWI on 1024 x 2 tiles takes the first
+// (10 VGPRs fewer there; elsewhere the run-time form measured faster).
+template <int MODE, typename RT, int NT, int PX, int NG, int OP, int FG, int PP, bool TAB = false>
 __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
     static_assert(PP == 1 || (PP == 2 && FG % 2 == 0) || (PP == 2 && FG == 1),
                   "frame pairs need an even frame group");
@@ -158,7 +162,11 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
                 rq[k][4 * q + 3] = v.w;
             }
     };
-    if (a.rx_tab && cb < ce) load_rq(cb);
+    if constexpr (TAB) {
+        if (cb < ce) load_rq(cb);
+    } else {
+        if (a.rx_tab && cb < ce) load_rq(cb);
+    }
     // per-transmit tables and the first chunk's bases (the last kChunk
     // threads), published by the first chunk's barrier
     tx_tables<MODE, NT, PX>(a, g, m_tab, q_tab);
@@ -236,7 +244,7 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         // pass (txr), copied aside when it is committed (txc); the plan
         // holds them for every shape but PWI on 1024 x 2 tiles
         constexpr bool kTxTab = FG == 1 && das_tx_words(MODE, NT, PX);
-        const bool tx_tab = kTxTab && a.tx_tabq != nullptr;
+        const bool tx_tab = TAB ? kTxTab : kTxTab && a.tx_tabq != nullptr;
         uint32_t txr[PP][PX], txc[PP][PX];
         auto issue = [&](int t, int g, int h) {  // pass t of frame frame0 + g into raw[h]
             const int at = __builtin_amdgcn_readfirstlane(m_tab[t].x);
@@ -307,10 +315,14 @@ __global__ void __launch_bounds__(NT) das_kernel(const DasArgs a) {
         int t1 = PP == 2 && FG == 1 ? next_active(t + 1) : te;  // second transmit of a pair
         if (PP == 2 && FG == 1 && t1 < te) issue(t1, 0, PP - 1);
         if (PP == 2 && FG > 1) issue(t, 1, PP - 1);  // second frame of a pair
-        if (a.rx_tab) {
+        if constexpr (TAB) {
             if (c0 != cb) load_rq(c0);
         } else {
-            rx_delays<PX>(a, p, c0, bj, rq);
+            if (a.rx_tab) {
+                if (c0 != cb) load_rq(c0);
+            } else {
+                rx_delays<PX>(a, p, c0, bj, rq);
+            }
         }
         int cur = 0;
         // two transmits per barrier: commit (t, t1) into buffers 2 cur and
@@ -508,13 +520,26 @@ hipError_t launch_one(const DasArgs& a, size_t lds, hipStream_t s) {
     // allocation would leave them outside the LDS it is given
     if (a.pp != PP || !das_lds_fits(lds, das_gather_nbuf(PP), a.slot, a.T))
         return hipErrorInvalidValue;
-    hipError_t e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
+    // PWI with delay tables on 1024 x 2 tiles launches the TAB variant; a
+    // prepared plan sets the LDS limit of both, so its calls, with or
+    // without the tables, make no attribute call
+    constexpr bool kTab = MODE == 1 && NT == 1024 && PX == 2;
+    const bool tab = kTab && a.rx_tab != nullptr;
+    hipError_t e = hipSuccess;
+    if (kTab && (a.prepare_only || tab))
+        e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, kTab>, lds);
+    if (e == hipSuccess && (a.prepare_only || !tab))
+        e = allow_lds(das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>, lds);
     if (e != hipSuccess || a.prepare_only) return e;
     const unsigned groups = (unsigned)((a.F + FG - 1) / FG);
     const dim3 grid = a.items ? dim3((unsigned)a.nitems, groups, 1u)
                               : dim3((unsigned)(a.ntz * a.ntx), groups, (unsigned)a.nsplit);
-    hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>), grid, dim3(NT), lds, s,
-                       a);
+    if (tab)
+        hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP, kTab>), grid, dim3(NT),
+                           lds, s, a);
+    else
+        hipLaunchKernelGGL((das_kernel<MODE, RT, NT, PX, NG, OP, FG, PP>), grid, dim3(NT), lds, s,
+                           a);
     return hipGetLastError();
 }
 

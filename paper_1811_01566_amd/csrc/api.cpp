@@ -254,9 +254,11 @@ constexpr size_t kLdsHard = 163840;
 // Tile plans a geometry can run: each (threads, pixels per thread) shape
 // and tile height whose window fits the gather's staging limits and whose
 // LDS leaves `min_waves` resident waves per CU.  Shapes: 1024 x 2 and 512 x 2
-// (two pixels a thread, 16 or 8 waves), 512 x 1 and 256 x 1 (half the tile,
-// a smaller window).  256 x 4 and 1024 x 1 cover the tiles of 512 x 2 with
-// fewer waves or one pixel a thread and measured slower on every geometry.
+// (two pixels a thread, 16 or 8 waves), 512 x 1 and 256 x 1 (a half and a
+// quarter of the 512 x 2 tile, smaller windows).  256 x 4 and 1024 x 1
+// cover the tiles of 512 x 2 with fewer waves or one pixel a thread, and
+// their gathers measured slower on every geometry (the adjoint still runs
+// 1024 x 1: plan_adjoint).
 std::vector<TilePlan> tile_candidates(const Geometry& g, const wf_acq* acq, const wf_grid* grid,
                                       int min_waves) {
     const int shapes[4][2] = {{1024, 2}, {512, 2}, {512, 1}, {256, 1}};

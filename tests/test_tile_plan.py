@@ -145,3 +145,18 @@ def test_planner_picks_the_measured_best_tiles(name):
     w = pool[name] if name in pool else phantom.get_workload(name)
     info = wf.tile_info(scan_from_workload(w), w.n_s, 1)
     assert (info["threads"], info["px"], info["tile_z"]) == MEASURED_BEST[name]
+
+
+def test_adjoint_tiles_served_mix():
+    """Over the served shape classes the adjoint's launch is the gather's, or
+    1024 x 1 threads over a 1024-pixel tile of the same family (its tile
+    height one the gather's candidates take), with a split of its own."""
+    for w in served_mix()[::3]:
+        info = wf.tile_info(scan_from_workload(w), w.n_s, 1)
+        adj = (info["adjoint_threads"], info["adjoint_px"])
+        gather = (info["threads"], info["px"])
+        assert adj == gather or adj == (1024, 1), (w.name, gather, adj)
+        if adj != gather:
+            assert gather[0] < 1024
+            assert info["adjoint_tile_z"] in (8, 16, 32, 64)
+        assert 1 <= info["adjoint_nsplit"] <= 64
